@@ -1,0 +1,134 @@
+"""Benchmark of the coupled ternary phase-field LB step on one MI355X.
+
+Default workload: the porous-medium displacement, a 4096 x 2048 D2Q9 domain
+of seeded random non-overlapping circles (radius U[8, 24], porosity 0.6,
+diffuse solid of width 3), FP32 storage and arithmetic, contact angle 45
+deg, density ratio 1, viscosity ratio 5, body force 1e-6 along x.  A step is
+one coupled update of both lattices at every node (one launch of the fused
+kernel).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: coupled MLUPS (whole-job), the roofline of the fused
+kernel (algorithmic bytes per launch / HIP-event kernel time against the
+8 TB/s HBM peak) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
+
+# HBM traffic of the fused kernel on this workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the factor a plain
+# copy kernel of known size gives; None until measured for the current kernel.
+PMC_TRAFFIC_BYTES = None
+
+
+def workload(name: str):
+    from paper_2311_05091_amd import geometry as G
+    if name == "porous_displacement":
+        return [G.porous_medium()], "porous_displacement_4096x2048"
+    if name == "cylinder_droplet":
+        return [G.cylinder_droplet()], "cylinder_droplet_1024x1024"
+    if name == "flat_wall_droplet":
+        return [G.flat_wall_droplet()], "flat_wall_droplet_128x64"
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(spec, steps: int):
+    """The FP64 oracle on the host cores: `steps` steps of the full domain."""
+    import oracle
+    oracle.build(force=False)
+    p = oracle.make_params(spec.nx, spec.ny, periodic_x=spec.periodic_x, periodic_y=spec.periodic_y,
+                           d0=spec.d0, D=spec.D, sigma12=spec.sigma12, theta_deg=spec.theta_deg,
+                           kappa=spec.kappa, rho=spec.rho, mu=spec.mu, M_cst=spec.M_cst,
+                           M_deg=spec.M_deg, tau_phi=spec.tau_phi, Fb=spec.Fb)
+    sim = oracle.Sim(p, spec.phi0, spec.phi1)
+    sim.step(1)  # first-touch of the pass buffers
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    n = spec.nx * spec.ny
+    return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d FP64 steps of the full %dx%d domain (after 1 untimed step)" % (steps, spec.nx, spec.ny)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="porous_displacement")
+    ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_05091_amd.lbm import Context
+
+    specs, wname = workload(args.workload)
+    nodes = sum(s.nx * s.ny for s in specs)
+    print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)
+    ctx = Context(precision=args.precision)
+    for s in specs:
+        ctx.add_domain(s)
+    ctx.finalize()
+    if args.tile:
+        ctx.set_tile(args.tile)
+    else:
+        ctx.autotune(steps=10)
+    code, tx, ty = ctx.tile()
+    print("[bench] tile %d (%dx%d)" % (code, tx, ty), flush=True)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.kernel_timing(False)
+    d = ctx.diag(0)
+    print("[bench] %d steps in %.3f s, kernel avg %.4f ms over %d launches, mass %.10e" %
+          (args.steps, dt, kern_ms, launches, d["mass"]), flush=True)
+
+    mlups = nodes * args.steps / dt / 1e6
+    bpn = ctx.bytes_per_node(0)
+    achieved = bpn * nodes / (kern_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": PMC_TRAFFIC_BYTES,
+            "bytes_per_node": bpn, "kernel_ms": round(kern_ms, 5)}
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
+        "config": {"workload": wname, "nodes": nodes, "lattice": "D2Q9 x 2 (CH + NS)",
+                   "tile": [tx, ty], "precision": args.precision},
+        "roofline": roof,
+    }
+    ctx.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline: oracle, %d steps" % args.cpu_steps, flush=True)
+        out["cpu_baseline"] = cpu_baseline(specs[0], args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

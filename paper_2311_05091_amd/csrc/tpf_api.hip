@@ -1,0 +1,939 @@
+// Host side of the C ABI declared in include/tpf.h: context and domain
+// management, per-domain constants (Sec. 2.2-3 of arXiv 2311.05091), arena
+// layout, launch of the fused step kernel over all live domains' tiles,
+// FP64 reductions, residual-driven retirement, checkpoints and the tile
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tpf.h"
+#include "tpf_kernels.h"
+
+namespace tpf {
+
+struct TileShape {
+    int code, tx, ty;
+};
+// codes are stable across builds; all use 256 threads (4 wavefronts)
+static const TileShape kTiles[] = {{1, 64, 4}, {2, 64, 8}, {3, 64, 16}, {4, 128, 8}, {5, 32, 8},
+                                   {6, 64, 32}, {7, 128, 16}};
+static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+static const int kDefaultTile = 3;
+
+struct HostDomain {
+    tpf_domain_params p;
+    std::vector<double> phi0, phi1;
+    DomDev dev;               // host copy of the device descriptor
+    int64_t steps = 0;
+    int32_t status = TPF_OK;  // TPF_OK, TPF_ENAN, or 1 = retired (residual)
+    double mass = NAN, residual = NAN, snap_norm = NAN;
+    int64_t snap_step = -1;
+    double k = 0, gamma[3] = {0, 0, 0}, gammaT = 0, eta = 0;
+    size_t off = 0, bytes = 0;  // arena slice
+};
+
+}  // namespace tpf
+
+using namespace tpf;
+
+struct tpf_ctx {
+    int precision = 64;
+    hipStream_t stream = nullptr;
+    std::vector<HostDomain> doms;
+    bool finalized = false;
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    bool own_arena = false;
+    // device-side tables inside the arena
+    DomDev* d_doms = nullptr;
+    int4* d_tiles = nullptr;
+    int* d_domlist = nullptr;
+    double* d_partials = nullptr;
+    double* d_red = nullptr;   // [ndom][4]
+    double* d_scratch = nullptr;  // max(4 N, 18 N) doubles
+    size_t max_tiles = 0;
+    int tile_code = kDefaultTile;
+    bool tile_from_user = false;
+    bool tuned = false;
+    int launch_mode = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    double t_acc_ms = 0;
+    int64_t t_launches = 0;
+    // current tile table
+    std::vector<int4> tiles;
+    std::vector<int> live_list;
+    int tiles_code_built = -1;
+    bool tiles_dirty = true;
+};
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static const TileShape* find_tile(int code) {
+    for (int i = 0; i < kNumTiles; ++i)
+        if (kTiles[i].code == code) return &kTiles[i];
+    return nullptr;
+}
+
+#define HIP_OK(expr)                                  \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) {                       \
+            std::fprintf(stderr, "tpf: %s failed: %s\n", #expr, hipGetErrorString(_e)); \
+            return TPF_EDEVICE;                       \
+        }                                             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Parameters and derived constants
+// ---------------------------------------------------------------------------
+extern "C" void tpf_default_params(tpf_domain_params* p, int32_t nx, int32_t ny) {
+    std::memset(p, 0, sizeof(*p));
+    p->nx = nx;
+    p->ny = ny;
+    p->periodic_x = 1;
+    p->periodic_y = 0;
+    p->d0 = 0.5;
+    p->D = 4.0;
+    p->sigma12 = 0.01;
+    p->theta = M_PI / 3.0;
+    p->kappa = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        p->rho[i] = 1.0;
+        p->mu[i] = 0.15;
+    }
+    p->M_cst = 0.0;
+    p->M_deg = 0.01;
+    p->tau_phi = 0.8;
+    for (int i = 0; i < 4; ++i) {
+        p->s_phi[i] = 1.0;
+        p->s_g[i] = 1.0;
+    }
+}
+
+// sigma01 = k sigma12 with k(theta, kappa) of Eq. (eq-kk); Young's law gives
+// sigma02; the spreading coefficients follow from the pairwise tensions.
+static void derive_gamma(const tpf_domain_params& p, double& k, double g[3], double& gT) {
+    const double th = p.theta;
+    const double sg = (th > 0.5 * M_PI) ? 1.0 : (th < 0.5 * M_PI ? -1.0 : 0.0);
+    const double sn = std::sin(0.25 * M_PI * std::cos(th));
+    k = 9.0 / (1.0 + p.kappa) * (1.0 + 2.0 * sg * sn * sn);
+    const double s12 = p.sigma12;
+    const double s01 = k * s12;
+    const double s02 = s01 + s12 * std::cos(th);
+    g[0] = s01 + s02 - s12;
+    g[1] = s01 + s12 - s02;
+    g[2] = s02 + s12 - s01;
+    gT = 3.0 / (1.0 / g[0] + 1.0 / g[1] + 1.0 / g[2]);
+}
+
+static int validate(const tpf_domain_params& p) {
+    if (p.nx < 3 || p.ny < 3) return TPF_EINVAL;
+    if ((int64_t)p.nx * p.ny * 9 >= (int64_t)1 << 31) return TPF_EINVAL;
+    if (!(p.theta > 0.0 && p.theta < M_PI)) return TPF_EINVAL;
+    if (!(p.d0 > 0.0 && p.d0 < 1.0)) return TPF_EINVAL;
+    if (!(p.tau_phi > 0.5)) return TPF_EINVAL;
+    if (!(p.D > 0.0) || !(p.sigma12 > 0.0)) return TPF_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (!(p.rho[i] > 0.0) || !(p.mu[i] > 0.0)) return TPF_EINVAL;
+    if (!(p.M_cst >= 0.0 && p.M_deg >= 0.0 && p.M_cst + p.M_deg > 0.0)) return TPF_EINVAL;
+    for (int i = 0; i < 4; ++i)
+        if (!(p.s_phi[i] > 0.0 && p.s_phi[i] < 2.0) || !(p.s_g[i] > 0.0 && p.s_g[i] < 2.0))
+            return TPF_EINVAL;
+    if (!(p.kappa > -1.0)) return TPF_EINVAL;
+    double k, g[3], gT;
+    derive_gamma(p, k, g, gT);
+    if (!(g[0] > 0 && g[1] > 0 && g[2] > 0)) return TPF_EINVAL;
+    return TPF_OK;
+}
+
+static void fill_constants(HostDomain& h) {
+    const tpf_domain_params& p = h.p;
+    DomDev& d = h.dev;
+    derive_gamma(p, h.k, h.gamma, h.gammaT);
+    const double c2 = p.d0;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.px = p.periodic_x ? 1 : 0;
+    d.py = p.periodic_y ? 1 : 0;
+    d.has_s = (p.rho[1] != p.rho[2]) ? 1 : 0;
+    d.c2 = c2;
+    d.w0 = (1.0 - c2) * (1.0 - c2);
+    d.gam0 = h.gamma[0];
+    d.gam1 = h.gamma[1];
+    d.gam2 = h.gamma[2];
+    d.gT3 = h.gammaT / 3.0;
+    d.inv_gam0 = 1.0 / h.gamma[0];
+    d.inv_gam2 = 1.0 / h.gamma[2];
+    d.c12D = 12.0 / p.D;
+    d.c3D4 = 0.75 * p.D;
+    // (M_cst + M_deg)/gamma_1 = (1/s1 - 1/2) eta c_s^2  (Sec. 3)
+    h.eta = (p.M_cst + p.M_deg) / (h.gamma[1] * (p.tau_phi - 0.5) * c2);
+    d.eta = h.eta;
+    d.Mcst = p.M_cst;
+    d.Mdeg = p.M_deg;
+    d.Mdeg_frac = p.M_deg / (p.M_cst + p.M_deg);
+    d.sphi[0] = p.s_phi[0];
+    d.sphi[1] = 1.0 / p.tau_phi;
+    d.sphi[2] = p.s_phi[1];
+    d.sphi[3] = p.s_phi[2];
+    d.sphi[4] = p.s_phi[3];
+    d.rho0 = p.rho[0];
+    d.rho1 = p.rho[1];
+    d.rho2 = p.rho[2];
+    d.muv0 = p.mu[0];
+    d.muv1 = p.mu[1];
+    d.muv2 = p.mu[2];
+    d.drho0 = p.rho[0] - p.rho[2];
+    d.drho1 = p.rho[1] - p.rho[2];
+    d.Sfac = (p.rho[1] - p.rho[2]) / h.gamma[1];
+    d.sg0 = p.s_g[0];
+    d.sg1 = p.s_g[1];
+    d.sg3 = p.s_g[2];
+    d.sg4 = p.s_g[3];
+    d.cfa = 0.5 * (1.0 - c2);
+    d.cfb = c2;
+    d.Fbx = p.Fb[0];
+    d.Fby = p.Fb[1];
+    d.uwx = p.u_wall[0];
+    d.uwy = p.u_wall[1];
+    d.gauge = p.rho_gauge;
+    // p = c_s^2/(1 - w0) [ sum_{i != 0} g_i + (1/2 + H) u.grad(rho)
+    //      - w0 (rho u - S).u/(c^2 - c_s^2) + (K/c^2)(dt/2) d_t((rho u - S).u) ]
+    // 2D: K = 1 - d0, H = K [ (1 - d0)/s0 - (2 - 4 d0)/s2a + (1 - 3 d0)/2 ]
+    d.pfac = c2 / (1.0 - d.w0);
+    d.pw = d.w0 / (1.0 - c2);
+    d.Kp = 1.0 - c2;
+    d.AH = (1.0 - c2) / p.s_g[0] + 0.5 * (1.0 - 3.0 * c2);
+    d.BH = 2.0 - 4.0 * c2;
+}
+
+// ---------------------------------------------------------------------------
+// Arena layout
+// ---------------------------------------------------------------------------
+static size_t domain_bytes(const HostDomain& h, int prec) {
+    const size_t e = prec == 32 ? 4 : 8;
+    const size_t N = (size_t)h.p.nx * h.p.ny;
+    const bool S = h.p.rho[1] != h.p.rho[2];
+    size_t b = 0;
+    b += align_up(4 * 9 * N * e, 256);       // f[2], g[2]
+    b += align_up(N * e, 256);               // phi0
+    b += align_up(2 * N * e, 256);           // A
+    b += align_up(N * e, 256);               // B
+    if (S) b += align_up(3 * N * e, 256) + align_up(2 * N * e, 256);  // C, psi[2]
+    b += align_up(N * 8, 256);               // snap (float64)
+    return b;
+}
+
+static void count_tiles(const tpf_ctx* c, size_t& max_tiles) {
+    max_tiles = 0;
+    for (int i = 0; i < kNumTiles; ++i) {
+        size_t t = 0;
+        for (auto& h : c->doms)
+            t += (size_t)((h.p.nx + kTiles[i].tx - 1) / kTiles[i].tx) *
+                 ((h.p.ny + kTiles[i].ty - 1) / kTiles[i].ty);
+        max_tiles = std::max(max_tiles, t);
+    }
+}
+
+static size_t max_nodes(const tpf_ctx* c) {
+    size_t m = 0;
+    for (auto& h : c->doms) m = std::max(m, (size_t)h.p.nx * h.p.ny);
+    return m;
+}
+
+static size_t total_bytes(tpf_ctx* c) {
+    size_t b = 0;
+    for (auto& h : c->doms) b += domain_bytes(h, c->precision);
+    size_t nd = c->doms.size();
+    size_t mt;
+    count_tiles(c, mt);
+    b += align_up(nd * sizeof(DomDev), 256);
+    b += align_up(mt * sizeof(int4), 256);
+    b += align_up(nd * sizeof(int), 256);
+    b += align_up(nd * kRedBlocks * 7 * sizeof(double), 256);
+    b += align_up(nd * 4 * sizeof(double), 256);
+    b += align_up(18 * max_nodes(c) * sizeof(double), 256);
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TY, bool S, int MODE>
+static hipError_t launch_step_t(tpf_ctx* c, int ntiles, int offset, double* mom) {
+    hipLaunchKernelGGL((step_kernel<T, TX, TY, 256, S, MODE>), dim3(ntiles), dim3(256), 0, c->stream,
+                       c->d_doms, c->d_tiles, ntiles, offset, mom);
+    return hipGetLastError();
+}
+
+template <typename T, bool S, int MODE>
+static hipError_t launch_step_shape(tpf_ctx* c, int code, int ntiles, int offset, double* mom) {
+    switch (code) {
+        case 1: return launch_step_t<T, 64, 4, S, MODE>(c, ntiles, offset, mom);
+        case 2: return launch_step_t<T, 64, 8, S, MODE>(c, ntiles, offset, mom);
+        case 3: return launch_step_t<T, 64, 16, S, MODE>(c, ntiles, offset, mom);
+        case 4: return launch_step_t<T, 128, 8, S, MODE>(c, ntiles, offset, mom);
+        case 5: return launch_step_t<T, 32, 8, S, MODE>(c, ntiles, offset, mom);
+        case 6: return launch_step_t<T, 64, 32, S, MODE>(c, ntiles, offset, mom);
+        case 7: return launch_step_t<T, 128, 16, S, MODE>(c, ntiles, offset, mom);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_step(tpf_ctx* c, bool anyS, int mode, int ntiles, int offset, double* mom) {
+    if (ntiles <= 0) return hipSuccess;
+    const int code = c->tile_code;
+    if (c->precision == 32) {
+        if (mode == kModeStep)
+            return anyS ? launch_step_shape<float, true, kModeStep>(c, code, ntiles, offset, mom)
+                        : launch_step_shape<float, false, kModeStep>(c, code, ntiles, offset, mom);
+        return anyS ? launch_step_shape<float, true, kModeMoments>(c, code, ntiles, offset, mom)
+                    : launch_step_shape<float, false, kModeMoments>(c, code, ntiles, offset, mom);
+    }
+    if (mode == kModeStep)
+        return anyS ? launch_step_shape<double, true, kModeStep>(c, code, ntiles, offset, mom)
+                    : launch_step_shape<double, false, kModeStep>(c, code, ntiles, offset, mom);
+    return anyS ? launch_step_shape<double, true, kModeMoments>(c, code, ntiles, offset, mom)
+                : launch_step_shape<double, false, kModeMoments>(c, code, ntiles, offset, mom);
+}
+
+// Host -> device upload of all descriptors (small; issued on the stream).
+static int upload_descriptors(tpf_ctx* c) {
+    std::vector<DomDev> v;
+    v.reserve(c->doms.size());
+    for (auto& h : c->doms) v.push_back(h.dev);
+    HIP_OK(hipMemcpyAsync(c->d_doms, v.data(), v.size() * sizeof(DomDev), hipMemcpyHostToDevice,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return TPF_OK;
+}
+
+// Tile table for a set of domains (all live ones, or one for moments).
+static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<int4>& out) {
+    const TileShape* ts = find_tile(c->tile_code);
+    out.clear();
+    for (int di : which) {
+        const auto& h = c->doms[di];
+        for (int y = 0; y < h.p.ny; y += ts->ty)
+            for (int x = 0; x < h.p.nx; x += ts->tx) out.push_back(make_int4(di, x, y, 0));
+    }
+    if (out.size() > c->max_tiles) return TPF_EINVAL;
+    if (!out.empty())
+        HIP_OK(hipMemcpyAsync(c->d_tiles, out.data(), out.size() * sizeof(int4),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return TPF_OK;
+}
+
+static bool any_s(const tpf_ctx* c, const std::vector<int>& which) {
+    for (int di : which)
+        if (c->doms[di].dev.has_s) return true;
+    return false;
+}
+
+static int refresh_live(tpf_ctx* c) {
+    std::vector<int> live;
+    for (size_t i = 0; i < c->doms.size(); ++i)
+        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+    if (live != c->live_list || c->tiles_dirty || c->tiles_code_built != c->tile_code) {
+        c->live_list = live;
+        int rc = build_tiles(c, live, c->tiles);
+        if (rc) return rc;
+        c->tiles_code_built = c->tile_code;
+        c->tiles_dirty = false;
+    }
+    return TPF_OK;
+}
+
+// Advances the live domains by n steps with one launch per step.  Domains
+// share the step count within the call, so each one's buffer parity is
+// (parity at entry + step index) & 1.
+static int run_steps(tpf_ctx* c, int64_t n) {
+    if (n <= 0) return TPF_OK;
+    int rc = refresh_live(c);
+    if (rc) return rc;
+    if (c->live_list.empty()) return TPF_OK;
+    for (int di : c->live_list) {
+        c->doms[di].dev.live = 1;
+    }
+    for (size_t i = 0; i < c->doms.size(); ++i)
+        if (c->doms[i].status != TPF_OK) c->doms[i].dev.live = 0;
+    rc = upload_descriptors(c);
+    if (rc) return rc;
+    const bool S = any_s(c, c->live_list);
+    const int ntiles = (int)c->tiles.size();
+    for (int64_t s = 0; s < n; ++s) {
+        const int off = (int)(s & 1);
+        if (c->timing) {
+            hipEvent_t a, b;
+            HIP_OK(hipEventCreate(&a));
+            HIP_OK(hipEventCreate(&b));
+            HIP_OK(hipEventRecord(a, c->stream));
+            HIP_OK(launch_step(c, S, kModeStep, ntiles, off, nullptr));
+            HIP_OK(hipEventRecord(b, c->stream));
+            c->ev_pool.push_back(a);
+            c->ev_pool.push_back(b);
+        } else {
+            HIP_OK(launch_step(c, S, kModeStep, ntiles, off, nullptr));
+        }
+    }
+    for (int di : c->live_list) {
+        auto& h = c->doms[di];
+        h.steps += n;
+        h.dev.parity = (int)((h.dev.parity + n) & 1);
+    }
+    return upload_descriptors(c);
+}
+
+// Mass and residual of the given domains (FP64, compensated).
+static int reduce(tpf_ctx* c, const std::vector<int>& which, bool update_snap) {
+    if (which.empty()) return TPF_OK;
+    HIP_OK(hipMemcpyAsync(c->d_domlist, which.data(), which.size() * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    dim3 grid(kRedBlocks, (unsigned)which.size());
+    if (c->precision == 32)
+        hipLaunchKernelGGL(reduce_partials<float>, grid, dim3(kRedThreads), 0, c->stream, c->d_doms,
+                           c->d_domlist, update_snap ? 1 : 0, c->d_partials);
+    else
+        hipLaunchKernelGGL(reduce_partials<double>, grid, dim3(kRedThreads), 0, c->stream, c->d_doms,
+                           c->d_domlist, update_snap ? 1 : 0, c->d_partials);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(reduce_final, dim3((which.size() + 63) / 64), dim3(64), 0, c->stream,
+                       c->d_domlist, (int)which.size(), c->d_partials, c->d_red);
+    HIP_OK(hipGetLastError());
+    std::vector<double> red(4 * c->doms.size());
+    HIP_OK(hipMemcpyAsync(red.data(), c->d_red, red.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    for (int di : which) {
+        auto& h = c->doms[di];
+        h.mass = red[4 * di + 0];
+        const double d2 = red[4 * di + 1], n2 = red[4 * di + 2], bad = red[4 * di + 3];
+        if (bad > 0 || !std::isfinite(h.mass)) h.status = TPF_ENAN;
+        if (update_snap) {
+            if (h.snap_step >= 0 && h.steps > h.snap_step && n2 > 0)
+                h.residual = std::sqrt(d2) / ((double)(h.steps - h.snap_step) * std::sqrt(n2));
+            h.snap_step = h.steps;
+        }
+    }
+    return TPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int tpf_create(tpf_ctx** out, int32_t precision, void* hip_stream) {
+    if (!out || (precision != 32 && precision != 64)) return TPF_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return TPF_EDEVICE;
+    tpf_ctx* c = new tpf_ctx();
+    c->precision = precision;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return TPF_OK;
+}
+
+extern "C" int tpf_add_domain(tpf_ctx* c, const tpf_domain_params* p, const double* phi0,
+                              const double* phi1, int32_t* id) {
+    if (!c || !p || !phi0 || !phi1) return TPF_EINVAL;
+    if (c->finalized) return TPF_ESTATE;
+    int rc = validate(*p);
+    if (rc) return rc;
+    HostDomain h;
+    h.p = *p;
+    const size_t N = (size_t)p->nx * p->ny;
+    h.phi0.assign(phi0, phi0 + N);
+    h.phi1.assign(phi1, phi1 + N);
+    fill_constants(h);
+    c->doms.push_back(std::move(h));
+    if (id) *id = (int32_t)c->doms.size() - 1;
+    return TPF_OK;
+}
+
+extern "C" int tpf_arena_bytes(tpf_ctx* c, uint64_t* bytes) {
+    if (!c || !bytes) return TPF_EINVAL;
+    if (c->doms.empty()) return TPF_ESTATE;
+    *bytes = total_bytes(c);
+    return TPF_OK;
+}
+
+static int init_domain(tpf_ctx* c, int di, const double* phi1) {
+    auto& h = c->doms[di];
+    const size_t N = (size_t)h.p.nx * h.p.ny;
+    HIP_OK(hipMemcpyAsync(c->d_scratch, phi1, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const int nb = (int)((N + 255) / 256);
+    if (c->precision == 32)
+        hipLaunchKernelGGL(init_kernel<float>, dim3(nb), dim3(256), 0, c->stream, c->d_doms, di,
+                           (const double*)c->d_scratch);
+    else
+        hipLaunchKernelGGL(init_kernel<double>, dim3(nb), dim3(256), 0, c->stream, c->d_doms, di,
+                           (const double*)c->d_scratch);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    h.steps = 0;
+    h.status = TPF_OK;
+    h.residual = NAN;
+    h.snap_step = -1;
+    return TPF_OK;
+}
+
+template <typename T>
+static int upload_phi0(tpf_ctx* c, HostDomain& h) {
+    std::vector<T> v(h.phi0.begin(), h.phi0.end());
+    HIP_OK(hipMemcpyAsync(h.dev.phi0, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return TPF_OK;
+}
+
+extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
+    if (!c) return TPF_EINVAL;
+    if (c->finalized) return TPF_ESTATE;
+    if (c->doms.empty()) return TPF_ESTATE;
+    const uint64_t need = total_bytes(c);
+    if (arena) {
+        if (arena_bytes < need || ((uintptr_t)arena & 255)) return TPF_EINVAL;
+        c->arena = (char*)arena;
+        c->own_arena = false;
+    } else {
+        void* p = nullptr;
+        HIP_OK(hipMalloc(&p, need));
+        c->arena = (char*)p;
+        c->own_arena = true;
+    }
+    c->arena_bytes = need;
+    const size_t e = c->precision == 32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* p = c->arena + off;
+        off += align_up(b, 256);
+        return (void*)p;
+    };
+    for (auto& h : c->doms) {
+        const size_t N = (size_t)h.p.nx * h.p.ny;
+        DomDev& d = h.dev;
+        char* base = (char*)take(4 * 9 * N * e);
+        d.f[0] = base;
+        d.f[1] = base + 9 * N * e;
+        d.g[0] = base + 18 * N * e;
+        d.g[1] = base + 27 * N * e;
+        d.phi0 = take(N * e);
+        d.lagA = take(2 * N * e);
+        d.lagB = take(N * e);
+        if (d.has_s) {
+            d.lagC = take(3 * N * e);
+            char* ps = (char*)take(2 * N * e);
+            d.psi[0] = ps;
+            d.psi[1] = ps + N * e;
+        } else {
+            d.lagC = nullptr;
+            d.psi[0] = d.psi[1] = nullptr;
+        }
+        d.snap = (double*)take(N * 8);
+        d.parity = 0;
+        d.live = 1;
+    }
+    size_t nd = c->doms.size();
+    count_tiles(c, c->max_tiles);
+    c->d_doms = (DomDev*)take(nd * sizeof(DomDev));
+    c->d_tiles = (int4*)take(c->max_tiles * sizeof(int4));
+    c->d_domlist = (int*)take(nd * sizeof(int));
+    c->d_partials = (double*)take(nd * kRedBlocks * 7 * sizeof(double));
+    c->d_red = (double*)take(nd * 4 * sizeof(double));
+    c->d_scratch = (double*)take(18 * max_nodes(c) * sizeof(double));
+    if (off > need) return TPF_EINVAL;
+    int rc = upload_descriptors(c);
+    if (rc) return rc;
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        rc = c->precision == 32 ? upload_phi0<float>(c, c->doms[i]) : upload_phi0<double>(c, c->doms[i]);
+        if (rc) return rc;
+        rc = init_domain(c, (int)i, c->doms[i].phi1.data());
+        if (rc) return rc;
+    }
+    c->finalized = true;
+    c->tiles_dirty = true;
+    std::vector<int> all(c->doms.size());
+    for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+    return reduce(c, all, true);
+}
+
+extern "C" int tpf_step(tpf_ctx* c, int64_t nsteps) {
+    if (!c || nsteps < 0) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    return run_steps(c, nsteps);
+}
+
+extern "C" int tpf_run_to_residual(tpf_ctx* c, double tol, int32_t check_every, int64_t max_steps,
+                                   int64_t* steps_out) {
+    if (!c || check_every <= 0 || max_steps < 0 || !(tol >= 0)) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    std::vector<int64_t> start(c->doms.size());
+    for (size_t i = 0; i < c->doms.size(); ++i) start[i] = c->doms[i].steps;
+    std::vector<int> live;
+    for (size_t i = 0; i < c->doms.size(); ++i)
+        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+    int rc = reduce(c, live, true);  // snapshot at entry
+    if (rc) return rc;
+    int64_t done = 0;
+    bool budget = false;
+    while (true) {
+        live.clear();
+        for (size_t i = 0; i < c->doms.size(); ++i)
+            if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+        if (live.empty()) break;
+        if (done >= max_steps) {
+            budget = true;
+            break;
+        }
+        const int64_t n = std::min<int64_t>(check_every, max_steps - done);
+        rc = run_steps(c, n);
+        if (rc) return rc;
+        done += n;
+        rc = reduce(c, live, true);
+        if (rc) return rc;
+        for (int di : live) {
+            auto& h = c->doms[di];
+            if (h.status == TPF_OK && std::isfinite(h.residual) && h.residual < tol) h.status = 1;
+        }
+    }
+    bool nan = false;
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        if (steps_out) steps_out[i] = c->doms[i].steps - start[i];
+        if (c->doms[i].status == TPF_ENAN) nan = true;
+        if (c->doms[i].status == 1) c->doms[i].status = TPF_OK;  // retired domains stay usable
+    }
+    // retired domains become live again for later calls
+    c->tiles_dirty = true;
+    if (nan) return TPF_ENAN;
+    return budget ? TPF_EBUDGET : TPF_OK;
+}
+
+extern "C" int tpf_read_moments(tpf_ctx* c, int32_t id, double* phi1, double* ux, double* uy, double* p) {
+    if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    auto& h = c->doms[id];
+    const size_t N = (size_t)h.p.nx * h.p.ny;
+    std::vector<int4> t;
+    std::vector<int> one = {id};
+    int rc = build_tiles(c, one, t);
+    if (rc) return rc;
+    c->tiles_dirty = true;
+    const bool S = h.dev.has_s != 0;
+    HIP_OK(launch_step(c, S, kModeMoments, (int)t.size(), 0, c->d_scratch));
+    std::vector<double> buf(4 * N);
+    HIP_OK(hipMemcpyAsync(buf.data(), c->d_scratch, 4 * N * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (phi1) std::memcpy(phi1, buf.data(), N * sizeof(double));
+    if (ux) std::memcpy(ux, buf.data() + N, N * sizeof(double));
+    if (uy) std::memcpy(uy, buf.data() + 2 * N, N * sizeof(double));
+    if (p) std::memcpy(p, buf.data() + 3 * N, N * sizeof(double));
+    return TPF_OK;
+}
+
+extern "C" int tpf_read_diag(tpf_ctx* c, int32_t id, double* mass, double* residual, int32_t* status,
+                             int64_t* steps) {
+    if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    std::vector<int> one = {id};
+    int rc = reduce(c, one, false);
+    if (rc) return rc;
+    auto& h = c->doms[id];
+    if (mass) *mass = h.mass;
+    if (residual) *residual = h.residual;
+    if (status) *status = h.status;
+    if (steps) *steps = h.steps;
+    return TPF_OK;
+}
+
+extern "C" int tpf_set_phi1(tpf_ctx* c, int32_t id, const double* phi1) {
+    if (!c || !phi1 || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    int rc = init_domain(c, id, phi1);
+    if (rc) return rc;
+    c->tiles_dirty = true;
+    std::vector<int> one = {id};
+    return reduce(c, one, true);
+}
+
+extern "C" int tpf_get_populations(tpf_ctx* c, int32_t id, double* f, double* g) {
+    if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    auto& h = c->doms[id];
+    const size_t N = (size_t)h.p.nx * h.p.ny;
+    if (c->precision == 32)
+        hipLaunchKernelGGL(export_populations<float>, dim3(1024), dim3(256), 0, c->stream, c->d_doms,
+                           id, c->d_scratch);
+    else
+        hipLaunchKernelGGL(export_populations<double>, dim3(1024), dim3(256), 0, c->stream, c->d_doms,
+                           id, c->d_scratch);
+    HIP_OK(hipGetLastError());
+    std::vector<double> buf(18 * N);
+    HIP_OK(hipMemcpyAsync(buf.data(), c->d_scratch, 18 * N * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (f) std::memcpy(f, buf.data(), 9 * N * sizeof(double));
+    if (g) std::memcpy(g, buf.data() + 9 * N, 9 * N * sizeof(double));
+    return TPF_OK;
+}
+
+// Checkpoint: a header, then per domain its host bookkeeping and its whole
+// arena slice (populations of both buffers, phi0, lagged fields, snapshot).
+static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '1'};
+
+static size_t domain_slice_bytes(const tpf_ctx* c, const HostDomain& h) {
+    return domain_bytes(h, c->precision);
+}
+
+extern "C" int tpf_save(tpf_ctx* c, const char* path) {
+    if (!c || !path) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return TPF_EIO;
+    int32_t hdr[3] = {c->precision, (int32_t)c->doms.size(), (int32_t)sizeof(tpf_domain_params)};
+    bool ok = std::fwrite(kMagic, 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1;
+    for (auto& h : c->doms) {
+        if (!ok) break;
+        const size_t b = domain_slice_bytes(c, h);
+        std::vector<char> buf(b);
+        if (hipMemcpyAsync(buf.data(), h.dev.f[0], b, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            std::fclose(fp);
+            return TPF_EDEVICE;
+        }
+        int64_t meta_i[3] = {h.steps, h.snap_step, (int64_t)h.status};
+        double meta_d[2] = {h.residual, h.mass};
+        int32_t par = h.dev.parity;
+        ok = std::fwrite(&h.p, sizeof(h.p), 1, fp) == 1 && std::fwrite(meta_i, sizeof(meta_i), 1, fp) == 1 &&
+             std::fwrite(meta_d, sizeof(meta_d), 1, fp) == 1 && std::fwrite(&par, 4, 1, fp) == 1 &&
+             std::fwrite(buf.data(), 1, b, fp) == b;
+    }
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? TPF_OK : TPF_EIO;
+}
+
+extern "C" int tpf_load(tpf_ctx* c, const char* path) {
+    if (!c || !path) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return TPF_EIO;
+    char magic[8];
+    int32_t hdr[3];
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(hdr, sizeof(hdr), 1, fp) == 1 && hdr[0] == c->precision &&
+              hdr[1] == (int32_t)c->doms.size() && hdr[2] == (int32_t)sizeof(tpf_domain_params);
+    for (auto& h : c->doms) {
+        if (!ok) break;
+        tpf_domain_params p;
+        int64_t meta_i[3];
+        double meta_d[2];
+        int32_t par;
+        const size_t b = domain_slice_bytes(c, h);
+        std::vector<char> buf(b);
+        ok = std::fread(&p, sizeof(p), 1, fp) == 1 && p.nx == h.p.nx && p.ny == h.p.ny &&
+             std::fread(meta_i, sizeof(meta_i), 1, fp) == 1 && std::fread(meta_d, sizeof(meta_d), 1, fp) == 1 &&
+             std::fread(&par, 4, 1, fp) == 1 && std::fread(buf.data(), 1, b, fp) == b;
+        if (!ok) break;
+        if (hipMemcpyAsync(h.dev.f[0], buf.data(), b, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            std::fclose(fp);
+            return TPF_EDEVICE;
+        }
+        h.steps = meta_i[0];
+        h.snap_step = meta_i[1];
+        h.status = (int32_t)meta_i[2];
+        h.residual = meta_d[0];
+        h.mass = meta_d[1];
+        h.dev.parity = par & 1;
+    }
+    std::fclose(fp);
+    if (!ok) return TPF_EIO;
+    c->tiles_dirty = true;
+    return upload_descriptors(c);
+}
+
+extern "C" int tpf_tile_codes(int32_t* n, int32_t* codes, int32_t* tx, int32_t* ty) {
+    if (!n) return TPF_EINVAL;
+    *n = kNumTiles;
+    for (int i = 0; i < kNumTiles; ++i) {
+        if (codes) codes[i] = kTiles[i].code;
+        if (tx) tx[i] = kTiles[i].tx;
+        if (ty) ty[i] = kTiles[i].ty;
+    }
+    return TPF_OK;
+}
+
+extern "C" int tpf_set_tile(tpf_ctx* c, int32_t code) {
+    if (!c) return TPF_EINVAL;
+    if (code == 0) {
+        c->tile_from_user = false;
+        c->tuned = false;
+        return TPF_OK;
+    }
+    if (!find_tile(code)) return TPF_EINVAL;
+    c->tile_code = code;
+    c->tile_from_user = true;
+    c->tiles_dirty = true;
+    return TPF_OK;
+}
+
+extern "C" int tpf_get_tile(tpf_ctx* c, int32_t* code, int32_t* tx, int32_t* ty) {
+    if (!c) return TPF_EINVAL;
+    const TileShape* t = find_tile(c->tile_code);
+    if (code) *code = t->code;
+    if (tx) *tx = t->tx;
+    if (ty) *ty = t->ty;
+    return TPF_OK;
+}
+
+extern "C" int tpf_autotune(tpf_ctx* c, int32_t steps, double* best_ms) {
+    if (!c || steps <= 0) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    // save the state of every domain (device slices + bookkeeping)
+    std::vector<std::vector<char>> saved(c->doms.size());
+    std::vector<HostDomain> meta = c->doms;
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        const size_t b = domain_slice_bytes(c, c->doms[i]);
+        saved[i].resize(b);
+        HIP_OK(hipMemcpyAsync(saved[i].data(), c->doms[i].dev.f[0], b, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    int best = c->tile_code;
+    double best_t = 1e300;
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    for (int i = 0; i < kNumTiles; ++i) {
+        c->tile_code = kTiles[i].code;
+        c->tiles_dirty = true;
+        int rc = run_steps(c, 2);  // warm-up (also builds the tile table)
+        if (rc) return rc;
+        HIP_OK(hipEventRecord(a, c->stream));
+        rc = run_steps(c, steps);
+        if (rc) return rc;
+        HIP_OK(hipEventRecord(b, c->stream));
+        HIP_OK(hipEventSynchronize(b));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, a, b));
+        const double per = ms / steps;
+        if (per < best_t) {
+            best_t = per;
+            best = kTiles[i].code;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        HIP_OK(hipMemcpyAsync(c->doms[i].dev.f[0], saved[i].data(), saved[i].size(), hipMemcpyHostToDevice,
+                              c->stream));
+        c->doms[i].steps = meta[i].steps;
+        c->doms[i].dev.parity = meta[i].dev.parity;
+        c->doms[i].status = meta[i].status;
+        c->doms[i].residual = meta[i].residual;
+        c->doms[i].snap_step = meta[i].snap_step;
+        c->doms[i].mass = meta[i].mass;
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->tile_code = best;
+    c->tuned = true;
+    c->tiles_dirty = true;
+    if (best_ms) *best_ms = best_t;
+    return upload_descriptors(c);
+}
+
+extern "C" int tpf_set_launch_mode(tpf_ctx* c, int32_t mode) {
+    if (!c || mode != 0) return TPF_EINVAL;  // the persistent mode is not built yet
+    c->launch_mode = mode;
+    return TPF_OK;
+}
+
+extern "C" int tpf_bytes_per_node(tpf_ctx* c, int32_t id, double* bytes) {
+    if (!c || !bytes || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    const double e = c->precision == 32 ? 4.0 : 8.0;
+    // 18 population reads + 18 writes, phi0, lagged A (2) and B (1) read + written,
+    // and with S: C (3) and psi (1) read + written
+    const double lag = c->doms[id].dev.has_s ? 7.0 : 3.0;
+    *bytes = e * (36.0 + 1.0 + 2.0 * lag);
+    return TPF_OK;
+}
+
+extern "C" int tpf_num_domains(tpf_ctx* c, int32_t* n) {
+    if (!c || !n) return TPF_EINVAL;
+    *n = (int32_t)c->doms.size();
+    return TPF_OK;
+}
+
+extern "C" int tpf_domain_size(tpf_ctx* c, int32_t id, int32_t* nx, int32_t* ny) {
+    if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (nx) *nx = c->doms[id].p.nx;
+    if (ny) *ny = c->doms[id].p.ny;
+    return TPF_OK;
+}
+
+extern "C" int tpf_derived(tpf_ctx* c, int32_t id, double* k, double* gamma3, double* gammaT, double* eta) {
+    if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    auto& h = c->doms[id];
+    double kk, g[3], gT;
+    derive_gamma(h.p, kk, g, gT);
+    if (k) *k = kk;
+    if (gamma3) std::memcpy(gamma3, g, sizeof(g));
+    if (gammaT) *gammaT = gT;
+    if (eta) *eta = (h.p.M_cst + h.p.M_deg) / (g[1] * (h.p.tau_phi - 0.5) * h.p.d0);
+    return TPF_OK;
+}
+
+extern "C" int tpf_kernel_timing(tpf_ctx* c, int32_t enable, double* avg_ms, int64_t* launches) {
+    if (!c) return TPF_EINVAL;
+    double acc = 0;
+    int64_t n = 0;
+    if (!c->ev_pool.empty()) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i + 1 < c->ev_pool.size(); i += 2) {
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+            acc += ms;
+            ++n;
+        }
+        for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+        c->ev_pool.clear();
+    }
+    if (avg_ms) *avg_ms = n ? acc / n : 0.0;
+    if (launches) *launches = n;
+    c->timing = enable != 0;
+    return TPF_OK;
+}
+
+extern "C" const char* tpf_strerror(int32_t s) {
+    switch (s) {
+        case TPF_OK: return "ok";
+        case TPF_EINVAL: return "invalid argument";
+        case TPF_EDEVICE: return "device error";
+        case TPF_ENAN: return "non-finite values in a domain";
+        case TPF_EBUDGET: return "step budget exhausted";
+        case TPF_ESTATE: return "call not valid in this state";
+        case TPF_EIO: return "checkpoint i/o error";
+    }
+    return "unknown status";
+}
+
+extern "C" void tpf_destroy(tpf_ctx* c) {
+    if (!c) return;
+    if (!c->ev_pool.empty()) {
+        (void)hipStreamSynchronize(c->stream);
+        for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    }
+    if (c->own_arena && c->arena) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->arena);
+    }
+    delete c;
+}

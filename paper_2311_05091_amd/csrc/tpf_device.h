@@ -1,0 +1,178 @@
+// Device-side building blocks of the coupled ternary phase-field LB step
+// (arXiv 2311.05091): per-domain descriptor, index maps, LDS stencils, the
+// D2Q9 natural/Hermite moment transforms and the per-node physics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpf {
+
+// D2Q9 velocities in the order of the rows of M0 (App. A):
+// 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1) 7 (-1,-1) 8 (1,-1)
+__device__ __constant__ const int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ __constant__ const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ __constant__ const int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Per-domain descriptor in device memory.  Pointers are element pointers of
+// the storage precision; constants are derived on the host in FP64.
+struct DomDev {
+    int32_t nx, ny, px, py;      // size and periodicity (1) / walls (0)
+    int32_t parity;              // buffer holding the current post-collision state
+    int32_t live;                // 1 while the domain is being advanced
+    int32_t has_s;               // rho1 != rho2: extra flux S, F_c and C are active
+    int32_t pad0;
+    void* f[2];                  // [9][ny][nx] CH populations (ping-pong)
+    void* g[2];                  // [9][ny][nx] NS populations (ping-pong)
+    void* phi0;                  // [ny][nx] solid field
+    void* lagA;                  // [2][ny][nx] phi1 u of the previous step
+    void* lagB;                  // [ny][nx]    (rho u - S).u of the previous step
+    void* lagC;                  // [3][ny][nx] sym(S u) of the previous step (has_s)
+    void* psi[2];                // [ny][nx]    S_x u_y - S_y u_x (has_s, ping-pong)
+    double* snap;                // [ny][nx]    phi1 at the last residual check
+    // lattice
+    double c2, w0;               // c_s^2 = d0, omega_0
+    // chemical potentials (Sec. 2.1)
+    double gam0, gam1, gam2, gT3;  // gamma_p, gamma^T/3
+    double inv_gam0, inv_gam2;
+    double c12D, c3D4;           // 12/D, 3D/4
+    // CH lattice (Sec. 3)
+    double eta, Mcst, Mdeg, Mdeg_frac;  // Mdeg_frac = M_deg/(M_cst + M_deg)
+    double sphi[5];              // s0, s1, s2, s3, s4
+    // NS lattice (Sec. 2.3, 3)
+    double rho0, rho1, rho2, muv0, muv1, muv2;
+    double drho0, drho1;         // rho0 - rho2, rho1 - rho2
+    double Sfac;                 // (rho1 - rho2)/gamma1
+    double sg0, sg1, sg3, sg4;
+    double cfa, cfb;             // (1 - c_s^2)/2 and c_s^2
+    double Fbx, Fby, uwx, uwy, gauge;
+    double pfac, pw, Kp, AH, BH; // p = pfac [ sum_{i>0} g_i + (1/2 + H) Q - pw B + Kp/2 dB ],
+                                 // H = Kp (AH - BH/s2a)
+};
+
+// Window cell -> node index.  Periodic axes wrap; across a half-way wall the
+// node is the even mirror (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).  Cells
+// farther out only occur in the unused part of a ragged tile's window and
+// are clamped so that every access stays inside the domain.
+__device__ __forceinline__ int map_index(int j, int n, int periodic) {
+    if (periodic) {
+        j %= n;
+        return j < 0 ? j + n : j;
+    }
+    if (j < 0) j = -1 - j;
+    else if (j >= n) j = 2 * n - 1 - j;
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// Pull-streamed population q at node (x, y): f*_q(x - c_q), or the opposite
+// post-collision population of the node itself across a wall (half-way
+// bounce-back, Sec. 4).
+template <typename T>
+__device__ __forceinline__ T pull(const T* __restrict__ fin, int q, int x, int y, int nx, int ny,
+                                  int px, int py, int N) {
+    int xs = x - kCx[q], ys = y - kCy[q];
+    bool out = false;
+    if (px) { xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs); }
+    else if (xs < 0 || xs >= nx) out = true;
+    if (py) { ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys); }
+    else if (ys < 0 || ys >= ny) out = true;
+    if (out) return fin[kOpp[q] * N + y * nx + x];
+    return fin[q * N + ys * nx + xs];
+}
+
+// Isotropic 9-point central gradient and Laplacian on a row-major LDS tile.
+template <typename T>
+__device__ __forceinline__ void stencil9(const T* s, int i, int W, T& gx, T& gy, T& lap) {
+    T C = s[i], E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
+    T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
+    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) / T(12);
+    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) / T(12);
+    lap = (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) / T(6);
+}
+
+template <typename T>
+__device__ __forceinline__ void grad9(const T* s, int i, int W, T& gx, T& gy) {
+    T E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
+    T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
+    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) / T(12);
+    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) / T(12);
+}
+
+template <typename T>
+__device__ __forceinline__ T lap9(const T* s, int i, int W) {
+    T C = s[i], E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
+    T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
+    return (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) / T(6);
+}
+
+// mu_p = gamma_p [ (12/D) phi (1-phi)(1-2phi) - (3D/4) lap(phi) ]   (Sec. 2.1)
+template <typename T>
+__device__ __forceinline__ T chem(T gam, T c12D, T c3D4, T phi, T lap) {
+    return gam * (c12D * phi * (T(1) - phi) * (T(1) - T(2) * phi) - c3D4 * lap);
+}
+
+// mubar_1 = (gamma^T/3) [ (mu1 - mu0)/gamma0 + (mu1 - mu2)/gamma2 ]  (Eq. eq-CHmodel)
+template <typename T>
+__device__ __forceinline__ T mubar1(const DomDev& d, T phi0, T phi1, T lap0, T lap1, T& mu0,
+                                    T& mu1, T& mu2) {
+    const T c12D = T(d.c12D), c3D4 = T(d.c3D4);
+    T phi2 = T(1) - phi0 - phi1;
+    mu0 = chem(T(d.gam0), c12D, c3D4, phi0, lap0);
+    mu1 = chem(T(d.gam1), c12D, c3D4, phi1, lap1);
+    mu2 = chem(T(d.gam2), c12D, c3D4, phi2, -lap0 - lap1);
+    return T(d.gT3) * ((mu1 - mu0) * T(d.inv_gam0) + (mu1 - mu2) * T(d.inv_gam2));
+}
+
+// Natural moments m = M0 p (rows 1, cx, cy, cx^2, cy^2, cxcy, cxcy^2, cx^2cy, cx^2cy^2).
+template <typename T>
+__device__ __forceinline__ void nat_moments(const T p[9], T m[9]) {
+    T a = p[5] + p[7], b = p[6] + p[8];
+    T c = p[5] - p[7], e = p[6] - p[8];
+    m[8] = a + b;
+    m[0] = p[0] + p[1] + p[2] + p[3] + p[4] + m[8];
+    m[1] = p[1] - p[3] + c - e;
+    m[2] = p[2] - p[4] + c + e;
+    m[3] = p[1] + p[3] + m[8];
+    m[4] = p[2] + p[4] + m[8];
+    m[5] = a - b;
+    m[6] = c - e;
+    m[7] = c + e;
+}
+
+// Hermite moments h = N m (App. A, c = 1).
+template <typename T>
+__device__ __forceinline__ void to_hermite(const T m[9], T h[9], T c2) {
+    h[0] = m[0];
+    h[1] = m[1];
+    h[2] = m[2];
+    h[3] = m[3] - c2 * m[0];
+    h[4] = m[4] - c2 * m[0];
+    h[5] = m[5];
+    h[6] = m[6] - c2 * m[1];
+    h[7] = m[7] - c2 * m[2];
+    h[8] = m[8] - c2 * (m[3] + m[4]) + c2 * c2 * m[0];
+}
+
+// Populations from Hermite moments: p = M0^-1 N^-1 h.
+template <typename T>
+__device__ __forceinline__ void from_hermite(const T h[9], T p[9], T c2) {
+    T m0 = h[0], m1 = h[1], m2 = h[2];
+    T m3 = h[3] + c2 * h[0];
+    T m4 = h[4] + c2 * h[0];
+    T m5 = h[5];
+    T m6 = h[6] + c2 * h[1];
+    T m7 = h[7] + c2 * h[2];
+    T m8 = h[8] + c2 * (m3 + m4) - c2 * c2 * m0;
+    p[0] = m0 - m3 - m4 + m8;
+    T a = m3 - m8, b = m1 - m6;
+    p[1] = T(0.5) * (a + b);
+    p[3] = T(0.5) * (a - b);
+    T c = m4 - m8, e = m2 - m7;
+    p[2] = T(0.5) * (c + e);
+    p[4] = T(0.5) * (c - e);
+    p[5] = T(0.25) * (m8 + m5 + m6 + m7);
+    p[6] = T(0.25) * (m8 - m5 - m6 + m7);
+    p[7] = T(0.25) * (m8 + m5 - m6 - m7);
+    p[8] = T(0.25) * (m8 - m5 + m6 - m7);
+}
+
+}  // namespace tpf

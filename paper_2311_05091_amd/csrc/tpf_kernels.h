@@ -1,0 +1,414 @@
+// Kernels of the coupled ternary phase-field LB step (arXiv 2311.05091, 2f1s
+// model, D2Q9, Hermite-moment collision).
+//
+// step_kernel: one workgroup per (domain, TX x TY tile).  In one pass it
+//   1. pulls the CH populations over the tile plus a 2-node halo and sums
+//      them into phi1 (LDS), next to phi0 (LDS);
+//   2. computes mubar1 on the tile plus a 1-node halo (LDS) and, when the
+//      flux S is active, stages the previous psi (LDS);
+//   3. per interior node: pulls f and g, forms grad/lap of phi0, phi1,
+//      grad(mubar1), the forces, u, p, relaxes both lattices in Hermite-moment
+//      space and writes the post-collision populations and lagged fields.
+// All global accesses are SoA rows with x fastest, so a wavefront of 64 lanes
+// touches 64 consecutive nodes.
+#pragma once
+#include "tpf_device.h"
+
+namespace tpf {
+
+enum StepMode { kModeStep = 0, kModeMoments = 1 };
+
+// Maps blockIdx.x to a logical tile so that each XCD (blocks are dealt to
+// the 8 XCDs round-robin) processes one contiguous band of tiles, whose
+// halos then hit in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    int q = G >> 3, r = G & 7;
+    int x = b & 7;
+    int start = x * q + (x < r ? x : r);
+    return start + (b >> 3);
+}
+
+template <typename T, int TX, int TY, int NT, bool HAS_S, int MODE>
+__global__ void __launch_bounds__(NT)
+step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+            int step_offset, double* __restrict__ mom_out) {
+    constexpr int WX = TX + 4, WY = TY + 4;  // halo-2 window
+    constexpr int VX = TX + 2, VY = TY + 2;  // halo-1 window
+    __shared__ T s_phi0[WX * WY];
+    __shared__ T s_phi1[WX * WY];
+    __shared__ T s_mub[VX * VY];
+    __shared__ T s_psi[HAS_S ? VX * VY : 1];
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int4 tile = tiles[t];
+    const DomDev& d = doms[tile.x];
+    if (!d.live && MODE == kModeStep) return;
+    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
+    const int N = nx * ny;
+    const int x0 = tile.y, y0 = tile.z;
+    const int cur = (d.parity + step_offset) & 1;
+    const T* __restrict__ fin = (const T*)d.f[cur];
+    const T* __restrict__ gin = (const T*)d.g[cur];
+    const T* __restrict__ phi0 = (const T*)d.phi0;
+    const int tid = threadIdx.x;
+
+    // ---- 1. phi0 and phi1 = sum_q f_q on the halo-2 window ----
+    for (int k = tid; k < WX * WY; k += NT) {
+        const int wx = k % WX, wy = k / WX;
+        const int sx = map_index(x0 - 2 + wx, nx, px);
+        const int sy = map_index(y0 - 2 + wy, ny, py);
+        s_phi0[k] = phi0[sy * nx + sx];
+        T s = pull(fin, 0, sx, sy, nx, ny, px, py, N);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) s += pull(fin, q, sx, sy, nx, ny, px, py, N);
+        s_phi1[k] = s;
+    }
+    __syncthreads();
+
+    // ---- 2. mubar1 (and the previous psi) on the halo-1 window ----
+    // HAS_S instances serve batches in which some domain has the flux S; the
+    // per-domain flag selects the branch (uniform across the workgroup)
+    const bool dS = HAS_S && d.has_s;
+    const T* __restrict__ psi_in = dS ? (const T*)d.psi[cur] : nullptr;
+    for (int k = tid; k < VX * VY; k += NT) {
+        const int vx = k % VX, vy = k / VX;
+        const int i = (vy + 1) * WX + (vx + 1);
+        T mu0, mu1, mu2;
+        s_mub[k] = mubar1<T>(d, s_phi0[i], s_phi1[i], lap9(s_phi0, i, WX), lap9(s_phi1, i, WX),
+                             mu0, mu1, mu2);
+        if (dS) {
+            const int sx = map_index(x0 - 1 + vx, nx, px);
+            const int sy = map_index(y0 - 1 + vy, ny, py);
+            s_psi[k] = psi_in[sy * nx + sx];
+        }
+    }
+    __syncthreads();
+
+    // ---- 3. per-node macroscopic fields and collisions ----
+    const T c2 = T(d.c2);
+    T* __restrict__ fout = (T*)d.f[cur ^ 1];
+    T* __restrict__ gout = (T*)d.g[cur ^ 1];
+    T* __restrict__ lagA = (T*)d.lagA;
+    T* __restrict__ lagB = (T*)d.lagB;
+    T* __restrict__ lagC = (T*)d.lagC;
+    T* __restrict__ psi_out = dS ? (T*)d.psi[cur ^ 1] : nullptr;
+
+    for (int k = tid; k < TX * TY; k += NT) {
+        const int lx = k % TX, ly = k / TX;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= nx || y >= ny) continue;
+        const int id = y * nx + x;
+        const int ip = (ly + 2) * WX + (lx + 2);
+        const int iv = (ly + 1) * VX + (lx + 1);
+
+        // phase fields and their stencils
+        const T ph0 = s_phi0[ip], ph1 = s_phi1[ip];
+        T gx0, gy0, lap0, gx1, gy1, lap1;
+        stencil9(s_phi0, ip, WX, gx0, gy0, lap0);
+        stencil9(s_phi1, ip, WX, gx1, gy1, lap1);
+        T mu0, mu1, mu2;
+        (void)mubar1<T>(d, ph0, ph1, lap0, lap1, mu0, mu1, mu2);
+        const T mub = s_mub[iv];
+        T gmx, gmy;
+        grad9(s_mub, iv, VX, gmx, gmy);
+
+        // degenerate mobility, 2f1s form f = phi1 (1 - phi1)(1 - phi0) (Sec. 4)
+        const T fdeg = ph1 * (T(1) - ph1) * (T(1) - ph0);
+        const T a = T(d.Mdeg_frac) * (T(1) - fdeg);
+
+        // density, viscosity (linear in phi_p), grad(rho)
+        const T ph2 = T(1) - ph0 - ph1;
+        const T rho = T(d.rho0) * ph0 + T(d.rho1) * ph1 + T(d.rho2) * ph2;
+        const T muv = T(d.muv0) * ph0 + T(d.muv1) * ph1 + T(d.muv2) * ph2;
+        const T drx = T(d.drho0) * gx0 + T(d.drho1) * gx1;
+        const T dry = T(d.drho0) * gy0 + T(d.drho1) * gy1;
+
+        // surface tension F_s = sum_p mu_p grad(phi_p)
+        T Fx = mu0 * gx0 + mu1 * gx1 + mu2 * (-gx0 - gx1);
+        T Fy = mu0 * gy0 + mu1 * gy1 + mu2 * (-gy0 - gy1);
+        T Sx = T(0), Sy = T(0);
+        if (dS) {
+            // S = (rho1 - rho2) M grad(mubar1)/gamma1; F_c from the previous psi
+            const T Mob = T(d.Mcst) + T(d.Mdeg) * fdeg;
+            Sx = T(d.Sfac) * Mob * gmx;
+            Sy = T(d.Sfac) * Mob * gmy;
+            T dpx, dpy;
+            grad9(s_psi, iv, VX, dpx, dpy);
+            Fx += T(-0.5) * dpy;
+            Fy += T(0.5) * dpx;
+        }
+        Fx += T(d.Fbx);
+        Fy += T(d.Fby);
+
+        // NS populations, moments; velocity with the solid correction (Sec. 3)
+        T gp[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gp[q] = pull(gin, q, x, y, nx, ny, px, py, N);
+        T mg[9];
+        nat_moments(gp, mg);
+        const T inv_rho = T(1) / rho;
+        const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
+        const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
+        const T fsx = T(d.uwx) - usx, fsy = T(d.uwy) - usy;
+        const T ux = usx + T(0.5) * ph0 * fsx;
+        const T uy = usy + T(0.5) * ph0 * fsy;
+
+        // per-node NS rates from mu/(rho (1 - phi0)) (Sec. 3)
+        const T om = T(1) - ph0;
+        const T s2a = om / (muv * inv_rho / T(d.cfa) + T(0.5) * om);
+        const T s2b = om / (muv * inv_rho / T(d.cfb) + T(0.5) * om);
+
+        // pressure (Sec. 3, 2D constants)
+        const T Q = ux * drx + uy * dry;
+        const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
+        const T Bp = lagB[id];
+        const T H = T(d.Kp) * (T(d.AH) - (d.BH == 0.0 ? T(0) : T(d.BH) / s2a));
+        const T p = T(d.pfac) * ((mg[0] - gp[0]) + (T(0.5) + H) * Q - T(d.pw) * Bn +
+                                 T(0.5) * T(d.Kp) * (Bn - Bp));
+
+        if constexpr (MODE == kModeMoments) {
+            mom_out[id] = double(ph1);
+            mom_out[N + id] = double(ux);
+            mom_out[2 * N + id] = double(uy);
+            mom_out[3 * N + id] = double(p);
+            continue;
+        }
+
+        // ---- CH collision in Hermite space ----
+        {
+            T fp[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fp[q] = pull(fin, q, x, y, nx, ny, px, py, N);
+            T m[9], h[9];
+            nat_moments(fp, m);
+            to_hermite(m, h, c2);
+            const T Ax = ph1 * ux, Ay = ph1 * uy;
+            const T emu = T(d.eta) * mub;
+            // d_t(phi u) by explicit Euler, plus the degenerate-mobility correction
+            const T Wx = (Ax - lagA[id]) + a * T(d.eta) * c2 * gmx;
+            const T Wy = (Ay - lagA[N + id]) + a * T(d.eta) * c2 * gmy;
+            const T s0 = T(d.sphi[0]), s1 = T(d.sphi[1]), s2 = T(d.sphi[2]);
+            const T s3 = T(d.sphi[3]), s4 = T(d.sphi[4]);
+            const T e3 = c2 * (emu - ph1);
+            h[0] = h[0] - s0 * (h[0] - ph1);
+            h[1] = h[1] - s1 * (h[1] - Ax) + (T(1) - T(0.5) * s1) * Wx;
+            h[2] = h[2] - s1 * (h[2] - Ay) + (T(1) - T(0.5) * s1) * Wy;
+            h[3] = h[3] - s2 * (h[3] - e3);
+            h[4] = h[4] - s2 * (h[4] - e3);
+            h[5] = h[5] - s2 * h[5];
+            h[6] = h[6] - s3 * h[6];
+            h[7] = h[7] - s3 * h[7];
+            h[8] = h[8] - s4 * (h[8] - c2 * c2 * (ph1 - emu));
+            from_hermite(h, fp, c2);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fout[q * N + id] = fp[q];
+            lagA[id] = Ax;
+            lagA[N + id] = Ay;
+        }
+
+        // ---- NS collision in Hermite space ----
+        {
+            const T Gx = Fx + ph0 * rho * fsx, Gy = Fy + ph0 * rho * fsy;
+            const T Jx = rho * ux, Jy = rho * uy;
+            const T Pxx = rho * ux * ux - Sx * ux;
+            const T Pyy = rho * uy * uy - Sy * uy;
+            const T Pxy = rho * ux * uy - T(0.5) * (Sx * uy + ux * Sy);
+            // M2F = uF + Fu - d_t((Su + uS)/2) + c_s^2 (u grad rho + grad rho u)
+            //       + (1 - 3 c_s^2)(u . grad rho) I
+            T Cxx = T(0), Cyy = T(0), Cxy = T(0), dCxx = T(0), dCyy = T(0), dCxy = T(0);
+            if (dS) {
+                Cxx = Sx * ux;
+                Cyy = Sy * uy;
+                Cxy = T(0.5) * (Sx * uy + Sy * ux);
+                dCxx = Cxx - lagC[id];
+                dCyy = Cyy - lagC[N + id];
+                dCxy = Cxy - lagC[2 * N + id];
+            }
+            const T q3 = (T(1) - T(3) * c2) * Q;
+            const T Mxx = T(2) * ux * Fx - dCxx + T(2) * c2 * ux * drx + q3;
+            const T Myy = T(2) * uy * Fy - dCyy + T(2) * c2 * uy * dry + q3;
+            const T Mxy = ux * Fy + Fx * uy - dCxy + c2 * (ux * dry + drx * uy);
+            T h[9];
+            to_hermite(mg, h, c2);
+            const T gauge = T(d.gauge);
+            const T sg0 = T(d.sg0), sg1 = T(d.sg1), sg3 = T(d.sg3), sg4 = T(d.sg4);
+            h[0] = h[0] - sg0 * (h[0] - gauge) + (T(1) - T(0.5) * sg0) * Q;
+            h[1] = h[1] - sg1 * (h[1] - Jx) + (T(1) - T(0.5) * sg1) * Gx;
+            h[2] = h[2] - sg1 * (h[2] - Jy) + (T(1) - T(0.5) * sg1) * Gy;
+            h[3] = h[3] - s2a * (h[3] - (p + Pxx - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Mxx;
+            h[4] = h[4] - s2a * (h[4] - (p + Pyy - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Myy;
+            h[5] = h[5] - s2b * (h[5] - Pxy) + (T(1) - T(0.5) * s2b) * Mxy;
+            h[6] = h[6] - sg3 * h[6];
+            h[7] = h[7] - sg3 * h[7];
+            h[8] = h[8] - sg4 * (h[8] - (c2 * c2 * gauge - c2 * p));
+            from_hermite(h, gp, c2);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) gout[q * N + id] = gp[q];
+            lagB[id] = Bn;
+            if (dS) {
+                lagC[id] = Cxx;
+                lagC[N + id] = Cyy;
+                lagC[2 * N + id] = Cxy;
+                psi_out[id] = Sx * uy - Sy * ux;
+            }
+        }
+    }
+}
+
+// Initial state (per node): f = f^eq(phi1, eta mubar1, u = 0), g = g^eq(P = 0,
+// u = 0) = gauge delta_q0, lagged fields zero.  phi1 comes from a float64 field.
+template <typename T>
+__global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const double* __restrict__ phi1_in) {
+    const DomDev& d = doms[dom];
+    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    const int x = id % nx, y = id / nx;
+    const T* phi0 = (const T*)d.phi0;
+    T v0[9], v1[9];
+    int k = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx, ++k) {
+            int sx = map_index(x + dx, nx, d.px), sy = map_index(y + dy, ny, d.py);
+            v0[k] = phi0[sy * nx + sx];
+            v1[k] = T(phi1_in[sy * nx + sx]);
+        }
+    // row-major 3x3 neighbourhood, centre at index 4, pitch 3
+    const T lap0 = lap9(v0, 4, 3), lap1 = lap9(v1, 4, 3);
+    T mu0, mu1, mu2;
+    const T mub = mubar1<T>(d, v0[4], v1[4], lap0, lap1, mu0, mu1, mu2);
+    const T c2 = T(d.c2), w0 = T(d.w0);
+    const T w1 = (c2 - c2 * c2) * T(0.5), w5 = c2 * c2 * T(0.25);
+    const T emu = T(d.eta) * mub;
+    const int par = d.parity;
+    T* f = (T*)d.f[par];
+    T* g = (T*)d.g[par];
+    f[id] = v1[4] + (w0 - T(1)) * emu;
+    for (int q = 1; q <= 4; ++q) f[q * N + id] = w1 * emu;
+    for (int q = 5; q <= 8; ++q) f[q * N + id] = w5 * emu;
+    g[id] = T(d.gauge);
+    for (int q = 1; q < 9; ++q) g[q * N + id] = T(0);
+    T* A = (T*)d.lagA;
+    A[id] = T(0);
+    A[N + id] = T(0);
+    ((T*)d.lagB)[id] = T(0);
+    if (d.has_s) {
+        T* C = (T*)d.lagC;
+        C[id] = T(0);
+        C[N + id] = T(0);
+        C[2 * N + id] = T(0);
+        ((T*)d.psi[0])[id] = T(0);
+        ((T*)d.psi[1])[id] = T(0);
+    }
+    d.snap[id] = __builtin_nan("");
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions with compensated (Neumaier/TwoSum) accumulation
+// ---------------------------------------------------------------------------
+struct CSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void csum_add(CSum& a, double v) {
+    double t = a.s + v;
+    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+    else a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void csum_merge(CSum& a, const CSum& b) {
+    csum_add(a, b.s);
+    a.c += b.c;
+}
+
+constexpr int kRedBlocks = 64;   // partial-sum blocks per domain
+constexpr int kRedThreads = 256;
+
+// Per domain (blockIdx.y), per node: phi1 = sum of the pulled CH populations;
+// accumulates sum phi1, sum (phi1 - snap)^2, sum phi1^2, a non-finite count,
+// and (when update_snap) stores phi1 into snap.  partials: [dom][block][7].
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_list, int update_snap,
+                double* __restrict__ partials) {
+    const int dom = dom_list[blockIdx.y];
+    const DomDev& d = doms[dom];
+    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    const T* fin = (const T*)d.f[d.parity];
+    CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
+    double bad = 0.0;
+    for (int id = blockIdx.x * kRedThreads + threadIdx.x; id < N; id += kRedBlocks * kRedThreads) {
+        const int x = id % nx, y = id / nx;
+        T s = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) s += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
+        const double v = double(s);
+        if (!isfinite(v)) bad += 1.0;
+        csum_add(m, v);
+        csum_add(n2, v * v);
+        const double prev = d.snap[id];
+        if (isfinite(prev)) csum_add(r, (v - prev) * (v - prev));
+        if (update_snap) d.snap[id] = v;
+    }
+    __shared__ double sh[7][kRedThreads];
+    sh[0][threadIdx.x] = m.s; sh[1][threadIdx.x] = m.c;
+    sh[2][threadIdx.x] = r.s; sh[3][threadIdx.x] = r.c;
+    sh[4][threadIdx.x] = n2.s; sh[5][threadIdx.x] = n2.c;
+    sh[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            for (int j = 0; j < 3; ++j) {
+                CSum a = {sh[2 * j][threadIdx.x], sh[2 * j + 1][threadIdx.x]};
+                CSum b = {sh[2 * j][o], sh[2 * j + 1][o]};
+                csum_merge(a, b);
+                sh[2 * j][threadIdx.x] = a.s;
+                sh[2 * j + 1][threadIdx.x] = a.c;
+            }
+            sh[6][threadIdx.x] += sh[6][o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7)
+        partials[((size_t)blockIdx.y * kRedBlocks + blockIdx.x) * 7 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// One thread per domain: folds the partials in a fixed order.
+// out: [dom][4] = mass, sum (phi1 - snap)^2, sum phi1^2, non-finite count.
+__global__ void reduce_final(const int* __restrict__ dom_list, int ndom, const double* __restrict__ partials,
+                             double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndom) return;
+    CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
+    double bad = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) {
+        const double* p = partials + ((size_t)j * kRedBlocks + b) * 7;
+        csum_merge(m, CSum{p[0], p[1]});
+        csum_merge(r, CSum{p[2], p[3]});
+        csum_merge(n2, CSum{p[4], p[5]});
+        bad += p[6];
+    }
+    const int dom = dom_list[j];
+    out[dom * 4 + 0] = m.s + m.c;
+    out[dom * 4 + 1] = r.s + r.c;
+    out[dom * 4 + 2] = n2.s + n2.c;
+    out[dom * 4 + 3] = bad;
+}
+
+// Copies the post-collision populations of one domain to float64 [2][9][N].
+template <typename T>
+__global__ void export_populations(const DomDev* __restrict__ doms, int dom, double* __restrict__ out) {
+    const DomDev& d = doms[dom];
+    const int N = d.nx * d.ny;
+    const T* f = (const T*)d.f[d.parity];
+    const T* g = (const T*)d.g[d.parity];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 9 * N; i += gridDim.x * blockDim.x) {
+        out[i] = double(f[i]);
+        out[9 * N + i] = double(g[i]);
+    }
+}
+
+}  // namespace tpf

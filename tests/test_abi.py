@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every function its headers declare
+(no compute: these run without a GPU)."""
+import ctypes
+import os
+
+import pytest
+
+from _util import header_functions
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2311_05091_amd")
+
+
+def _lib(name):
+    path = os.path.join(PKG, name)
+    if not os.path.exists(path):
+        from paper_2311_05091_amd import build
+        build.build_all()
+    return ctypes.CDLL(path)
+
+
+def test_tpf_exports_every_declared_symbol():
+    names = header_functions(os.path.join(ROOT, "include", "tpf.h"))
+    assert "tpf_step" in names and "tpf_create" in names and len(names) >= 20
+    lib = _lib("libtpf.so")
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_python_binding_covers_header():
+    from paper_2311_05091_amd import lbm
+    names = header_functions(os.path.join(ROOT, "include", "tpf.h"))
+    assert sorted(lbm.EXPORTED) == names
+
+
+def test_strerror_and_tile_table_without_device():
+    lib = _lib("libtpf.so")
+    lib.tpf_strerror.restype = ctypes.c_char_p
+    assert lib.tpf_strerror(-3).decode() == "non-finite values in a domain"
+    n = ctypes.c_int32()
+    assert lib.tpf_tile_codes(ctypes.byref(n), None, None, None) == 0 and n.value >= 4
+
+
+def test_default_params_are_stable_reading():
+    from paper_2311_05091_amd import lbm
+    lib = lbm.library()
+    p = lbm.DomainParams()
+    lib.tpf_default_params(ctypes.byref(p), 128, 64)
+    assert (p.nx, p.ny, p.periodic_x, p.periodic_y) == (128, 64, 1, 0)
+    assert p.d0 == 0.5 and p.tau_phi == 0.8 and p.M_deg == 0.01 and p.rho_gauge == 0.0

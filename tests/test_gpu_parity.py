@@ -1,0 +1,144 @@
+"""Parity of the HIP library with the FP64 oracle (run on an MI355X).
+
+Element-by-element comparison of phi1, u, p (and the raw populations) on the
+same seeded inputs, on sizes that span several tiles with ragged tails, with
+periodic axes and bounce-back walls, with and without the extra flux S
+(density ratio != 1), and under every tile shape of the fused kernel.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2311_05091_amd import geometry as G
+from paper_2311_05091_amd import measure as Me
+from _util import gpu_context, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(ctx, sim, did=0, tol=1e-12, pop_tol=1e-12):
+    g = ctx.moments(did)
+    o = sim.moments()
+    for name, a, b in zip(("phi1", "ux", "uy", "p"), g, o):
+        assert np.isfinite(a).all(), name
+        scale = max(np.abs(b).max(), 1e-300)
+        err = np.abs(a - b).max() / scale
+        assert err <= tol, (name, err)
+    fo, go, _ = sim.get_state()
+    fg, gg = ctx.populations(did)
+    assert np.abs(fg - fo).max() <= pop_tol * max(1.0, np.abs(fo).max())
+    assert np.abs(gg - go).max() <= pop_tol * max(1e-3, np.abs(go).max())
+
+
+CASES = [
+    # name, spec factory, steps
+    ("disk16_periodic_S", lambda: G.solid_disk_box(n=16, rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015)), 200),
+    ("disk16_periodic", lambda: G.solid_disk_box(n=16), 200),
+    ("disk16_walls_S", lambda: G.solid_disk_box(n=16, periodic_y=0, rho=(1.0, 1.0, 0.1),
+                                                mu=(0.15, 0.15, 0.015)), 200),
+    ("ragged_67x23_walls", lambda: G.solid_disk_box(n=67, ny=23, Rs=5.0, R0=6.0, periodic_y=0), 150),
+    ("ragged_131x37_S", lambda: G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0,
+                                                 rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015)), 150),
+    ("flat_wall_small", lambda: G.flat_wall_droplet(nx=96, ny=40, wall_rows=6, R0=14), 300),
+    ("body_force_d0_04", lambda: G.with_params(G.solid_disk_box(n=40, ny=20, periodic_y=0), d0=0.4,
+                                               Fb=(1e-5, -2e-6), rho_gauge=0.3), 150),
+]
+
+
+@pytest.mark.parametrize("name,factory,steps", CASES, ids=[c[0] for c in CASES])
+def test_fp64_parity(orc, name, factory, steps):
+    sp = factory()
+    _say("fp64 parity", name, sp.nx, sp.ny, steps)
+    ctx = gpu_context([sp], precision=64)
+    ctx.step(steps)
+    sim = oracle_run(orc, sp, steps)
+    _compare(ctx, sim, tol=1e-11, pop_tol=1e-12)
+    ctx.close()
+
+
+def test_every_tile_shape_identical(orc):
+    """The tile shape changes only the work decomposition, not a single bit."""
+    from paper_2311_05091_amd.lbm import tile_codes
+    sp = G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0, rho=(1.0, 1.0, 0.1),
+                          mu=(0.15, 0.15, 0.015))
+    ref = {}
+    for code, tx, ty in tile_codes():
+        _say("tile", code, tx, ty)
+        for prec in (32, 64):
+            ctx = gpu_context([sp], precision=prec, tile=code)
+            ctx.step(40)
+            f, g = ctx.populations(0)
+            ctx.close()
+            if prec not in ref:
+                ref[prec] = (f, g)
+            else:
+                assert np.array_equal(f, ref[prec][0]) and np.array_equal(g, ref[prec][1]), (code, prec)
+
+
+def test_initial_state_matches_oracle(orc):
+    sp = G.flat_wall_droplet(nx=70, ny=30, wall_rows=5, R0=10)
+    _say("init", sp.nx, sp.ny)
+    ctx = gpu_context([sp], precision=64)
+    sim = oracle_run(orc, sp, 0)
+    _compare(ctx, sim, tol=1e-13, pop_tol=1e-14)
+    ctx.close()
+
+
+def test_config1_fp64_5000_steps(orc):
+    """Flat-wall droplet 128x64, theta = 60 deg, 5000 steps: rel L2 of phi and u <= 1e-5."""
+    sp = G.flat_wall_droplet()
+    _say("config1 fp64 5000")
+    ctx = gpu_context([sp], precision=64)
+    ctx.step(5000)
+    phi_g, ux_g, uy_g, p_g = ctx.moments(0)
+    sim = oracle_run(orc, sp, 5000)
+    phi_o, ux_o, uy_o, p_o = sim.moments()
+    assert rel_l2(phi_g, phi_o) <= 1e-5
+    u_g = np.stack([ux_g, uy_g])
+    u_o = np.stack([ux_o, uy_o])
+    assert rel_l2(u_g, u_o) <= 1e-5
+    assert rel_l2(p_g, p_o) <= 1e-5
+    ctx.close()
+
+
+def test_config1_fp32_contact_angle(orc):
+    """FP32 offset storage: the contact angle after 5000 steps is within 0.5 deg of the
+    FP64 oracle's, and rel L2 errors of phi and u are small."""
+    sp = G.flat_wall_droplet()
+    _say("config1 fp32 5000")
+    ctx = gpu_context([sp], precision=32)
+    ctx.step(5000)
+    phi_g, ux_g, uy_g, p_g = ctx.moments(0)
+    sim = oracle_run(orc, sp, 5000)
+    phi_o, ux_o, uy_o, p_o = sim.moments()
+    th_g = Me.droplet_on_flat_wall(phi_g, 7.5, sp.D)["theta_deg"]
+    th_o = Me.droplet_on_flat_wall(phi_o, 7.5, sp.D)["theta_deg"]
+    print("theta fp32 %.4f oracle %.4f" % (th_g, th_o))
+    assert abs(th_g - th_o) <= 0.5
+    assert rel_l2(phi_g, phi_o) <= 1e-3
+    assert rel_l2(np.stack([ux_g, uy_g]), np.stack([ux_o, uy_o])) <= 5e-2
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-12), (32, 2e-6)])
+def test_mass_conservation(prec, tol):
+    """Sum of phi1 after 2000 steps (FP64 compensated reduction on the device)."""
+    sp = G.solid_disk_box(n=96, ny=64, Rs=10, R0=14, periodic_y=0, rho=(1.0, 1.0, 0.1),
+                          mu=(0.15, 0.15, 0.015))
+    _say("mass", prec)
+    ctx = gpu_context([sp], precision=prec)
+    m0 = ctx.diag(0)["mass"]
+    assert abs(m0 - sp.phi1.sum()) <= (1e-13 if prec == 64 else 1e-6) * sp.phi1.sum()
+    ctx.step(2000)
+    d = ctx.diag(0)
+    phi = ctx.moments(0)[0]
+    assert abs(d["mass"] - phi.sum()) <= 1e-12 * abs(phi.sum())
+    assert abs(d["mass"] - m0) <= tol * m0, (d["mass"] - m0) / m0
+    ctx.close()
