@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=256,
+                    help="size of the plain device copy run once before the steps; its "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -79,6 +82,14 @@ def main():
 
     import torch
     from paper_2311_05091_amd.lbm import Context
+
+    if args.copy_mib > 0:
+        # reference copy kernel of known size (reads and writes copy_mib MiB)
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     specs, wname = workload(args.workload)
     nodes = sum(s.nx * s.ny for s in specs)
