@@ -1,0 +1,109 @@
+/*
+ * tpf_nn.h -- C ABI of the kernels behind the learned warm start: a small
+ * convolutional encoder-decoder that predicts the equilibrium phase field
+ * phi1 from the solid field phi0, a contact-angle map and the droplet volume,
+ * trained on equilibria that the lattice Boltzmann library itself computes.
+ * The LB method then relaxes from the prediction (Zhan, Chai & Shi, arXiv
+ * 2311.05091, supplies the LB method; the network is not part of the paper).
+ *
+ * Conventions
+ *   - All pointers are device pointers; sizes are element counts.  Tensors
+ *     are NHWC (channels fastest).  Activations and gradients flowing through
+ *     the network are bfloat16 (stored as uint16_t); weights have an FP32
+ *     master copy and a bf16 copy; all products accumulate in FP32 on the
+ *     BF16 matrix cores (v_mfma_f32_16x16x32_bf16).
+ *   - Convolution weights are [Cout][3][3][Cin]; channel counts of the
+ *     matrix-core paths must be multiples of 32; H*W must be a multiple of 64.
+ *   - Every function enqueues on `stream` (a hipStream_t, NULL = default) and
+ *     returns 0, or TPF_EINVAL (-1) for shapes the kernels do not support,
+ *     or TPF_EDEVICE (-2) for a launch failure.  Nothing is allocated.
+ */
+#ifndef TPF_NN_H
+#define TPF_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* D = A B for one 16x32 (row-major bf16) by 32x16 (row-major bf16) product
+ * on one wavefront's matrix core; D is 16x16 row-major FP32.  Checks the
+ * operand layout the convolution kernels rely on. */
+int tpfnn_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* stream);
+
+/* y[n,h,w,co] = act(bias[co] + sum_{ky,kx,ci} w[co,ky,kx,ci] x[n,h+ky-1,w+kx-1,ci]),
+ * zero padding, act = ReLU when relu != 0.  bias may be NULL.  Cin, Cout
+ * multiples of 32. */
+int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t Cin,
+                      const uint16_t* w, const float* bias, int32_t Cout, int32_t relu,
+                      uint16_t* y, void* stream);
+
+/* wt[ci,ky,kx,co] = w[co,2-ky,2-kx,ci] (bf16): the weights of the input-gradient
+ * convolution, dx = conv3x3(dy, wt). */
+int tpfnn_weight_flip(const uint16_t* w, int32_t Cout, int32_t Cin, uint16_t* wt, void* stream);
+
+/* dw[co,ky,kx,ci] = sum_{n,h,w} dy[n,h,w,co] x[n,h+ky-1,w+kx-1,ci] and, when db is
+ * not NULL, db[co] = sum dy[...,co]; both FP32, overwritten.  work must hold
+ * tpfnn_wgrad_workspace(...) bytes (split-K partial sums, reduced in a fixed
+ * order so that the result is deterministic). */
+size_t tpfnn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout);
+int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_t N, int32_t H, int32_t W,
+                        int32_t Cin, int32_t Cout, float* dw, float* db, void* work,
+                        size_t work_bytes, void* stream);
+
+/* dy *= (y > 0), in place (backward of ReLU given its output y). */
+int tpfnn_relu_bwd(const uint16_t* y, uint16_t* dy, int64_t n, void* stream);
+
+/* 2x2 average pooling and its adjoint (NHWC, H and W even). */
+int tpfnn_avgpool2_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* y,
+                       void* stream);
+int tpfnn_avgpool2_bwd(const uint16_t* dy, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* dx,
+                       void* stream);
+/* nearest 2x upsampling of an [N,H,W,C] tensor and its adjoint (sum of 4). */
+int tpfnn_upsample2_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* y,
+                        void* stream);
+int tpfnn_upsample2_bwd(const uint16_t* dy, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* dx,
+                        void* stream);
+/* channel concatenation y = [a | b] and its adjoint (split). */
+int tpfnn_concat(const uint16_t* a, int32_t Ca, const uint16_t* b, int32_t Cb, int64_t npix,
+                 uint16_t* y, void* stream);
+int tpfnn_split(const uint16_t* dy, int32_t Ca, int32_t Cb, int64_t npix, uint16_t* da,
+                uint16_t* db, void* stream);
+/* a += b elementwise (gradient accumulation of a tensor used twice). */
+int tpfnn_add_inplace(uint16_t* a, const uint16_t* b, int64_t n, void* stream);
+
+/* Output head: z = b + sum_c w[c] x[p,c], pred = sigmoid(z) (FP32).  When target
+ * is not NULL also: loss = mean_p (pred - target)^2 (FP64, deterministic),
+ * dx[p,c] = dz w[c] (bf16), dw[c] = sum_p dz x[p,c], db = sum_p dz (FP32),
+ * dz = 2 (pred - target) pred (1 - pred)/npix.  work must hold
+ * tpfnn_head_workspace(npix, C) bytes. */
+size_t tpfnn_head_workspace(int64_t npix, int32_t C);
+int tpfnn_head(const uint16_t* x, int64_t npix, int32_t C, const float* w, const float* b,
+               float* pred, const float* target, uint16_t* dx, float* dw, float* db, double* loss,
+               void* work, size_t work_bytes, void* stream);
+
+/* Adam with bias correction on FP32 master weights; also writes the bf16 copy
+ * (p_bf16 may be NULL).  t is the 1-based step count. */
+int tpfnn_adam(float* p, float* m, float* v, const float* g, uint16_t* p_bf16, int64_t n, float lr,
+               float beta1, float beta2, float eps, int32_t t, void* stream);
+
+/* FP32 -> bf16 (round to nearest even) and back. */
+int tpfnn_to_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
+int tpfnn_from_bf16(const uint16_t* x, float* y, int64_t n, void* stream);
+
+/* Bilinear resampling of N single-channel fields [N,sh,sw] -> [N,dh,dw]
+ * (FP32, align-corners sampling: the corner nodes map onto each other). */
+int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* dst, int32_t dh,
+                   int32_t dw, void* stream);
+
+/* Network input from physical fields: x[n,h,w,:] = (phi0, (theta - 90 deg)/60 deg,
+ * volume scale, 0, ..., 0) padded to 32 channels (bf16). */
+int tpfnn_pack_input(const float* phi0, const float* theta_deg, const float* vol, int32_t N,
+                     int32_t H, int32_t W, uint16_t* x, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPF_NN_H */

@@ -20,13 +20,17 @@
 namespace tpf {
 
 struct TileShape {
-    int code, tx, ty;
+    int code, tx, ty, threads;
 };
-// codes are stable across builds; all use 256 threads (4 wavefronts)
-static const TileShape kTiles[] = {{1, 64, 4}, {2, 64, 8}, {3, 64, 16}, {4, 128, 8}, {5, 32, 8},
-                                   {6, 64, 32}, {7, 128, 16}};
+// codes are stable across builds.  1-7: tile kernel (256 threads, whole-tile
+// LDS window); 8-11: strip kernel (one wavefront marching down a 64-column
+// strip of ty rows).
+static const TileShape kTiles[] = {{1, 64, 4, 256},  {2, 64, 8, 256},   {3, 64, 16, 256},
+                                   {4, 128, 8, 256}, {5, 32, 8, 256},   {6, 64, 32, 256},
+                                   {7, 128, 16, 256}, {8, 64, 16, 64},  {9, 64, 32, 64},
+                                   {10, 64, 64, 64}, {11, 64, 128, 64}};
 static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
-static const int kDefaultTile = 3;
+static const int kDefaultTile = 9;
 
 struct HostDomain {
     tpf_domain_params p;
@@ -71,6 +75,7 @@ struct tpf_ctx {
     int64_t t_launches = 0;
     // current tile table
     std::vector<int4> tiles;
+    int tiles_noS = 0;  // tiles of domains without S come first
     std::vector<int> live_list;
     int tiles_code_built = -1;
     bool tiles_dirty = true;
@@ -260,7 +265,7 @@ static size_t total_bytes(tpf_ctx* c) {
     b += align_up(nd * sizeof(DomDev), 256);
     b += align_up(mt * sizeof(int4), 256);
     b += align_up(nd * sizeof(int), 256);
-    b += align_up(nd * kRedBlocks * 7 * sizeof(double), 256);
+    b += align_up(nd * kRedMaxBlocks * 7 * sizeof(double), 256);
     b += align_up(nd * 4 * sizeof(double), 256);
     b += align_up(18 * max_nodes(c) * sizeof(double), 256);
     return b;
@@ -270,41 +275,62 @@ static size_t total_bytes(tpf_ctx* c) {
 // Launch helpers
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, bool S, int MODE>
-static hipError_t launch_step_t(tpf_ctx* c, int ntiles, int offset, double* mom) {
+static hipError_t launch_step_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
     hipLaunchKernelGGL((step_kernel<T, TX, TY, 256, S, MODE>), dim3(ntiles), dim3(256), 0, c->stream,
-                       c->d_doms, c->d_tiles, ntiles, offset, mom);
+                       c->d_doms, c->d_tiles + t0, ntiles, offset, mom);
+    return hipGetLastError();
+}
+
+template <typename T, int CH, bool S, int MODE>
+static hipError_t launch_strip_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
+    hipLaunchKernelGGL((strip_kernel<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
+                       c->d_tiles + t0, ntiles, offset, mom);
     return hipGetLastError();
 }
 
 template <typename T, bool S, int MODE>
-static hipError_t launch_step_shape(tpf_ctx* c, int code, int ntiles, int offset, double* mom) {
+static hipError_t launch_step_shape(tpf_ctx* c, int code, int t0, int n, int offset, double* mom) {
     switch (code) {
-        case 1: return launch_step_t<T, 64, 4, S, MODE>(c, ntiles, offset, mom);
-        case 2: return launch_step_t<T, 64, 8, S, MODE>(c, ntiles, offset, mom);
-        case 3: return launch_step_t<T, 64, 16, S, MODE>(c, ntiles, offset, mom);
-        case 4: return launch_step_t<T, 128, 8, S, MODE>(c, ntiles, offset, mom);
-        case 5: return launch_step_t<T, 32, 8, S, MODE>(c, ntiles, offset, mom);
-        case 6: return launch_step_t<T, 64, 32, S, MODE>(c, ntiles, offset, mom);
-        case 7: return launch_step_t<T, 128, 16, S, MODE>(c, ntiles, offset, mom);
+        case 8: return launch_strip_t<T, 16, S, MODE>(c, t0, n, offset, mom);
+        case 9: return launch_strip_t<T, 32, S, MODE>(c, t0, n, offset, mom);
+        case 10: return launch_strip_t<T, 64, S, MODE>(c, t0, n, offset, mom);
+        case 11: return launch_strip_t<T, 128, S, MODE>(c, t0, n, offset, mom);
+        case 1: return launch_step_t<T, 64, 4, S, MODE>(c, t0, n, offset, mom);
+        case 2: return launch_step_t<T, 64, 8, S, MODE>(c, t0, n, offset, mom);
+        case 3: return launch_step_t<T, 64, 16, S, MODE>(c, t0, n, offset, mom);
+        case 4: return launch_step_t<T, 128, 8, S, MODE>(c, t0, n, offset, mom);
+        case 5: return launch_step_t<T, 32, 8, S, MODE>(c, t0, n, offset, mom);
+        case 6: return launch_step_t<T, 64, 32, S, MODE>(c, t0, n, offset, mom);
+        case 7: return launch_step_t<T, 128, 16, S, MODE>(c, t0, n, offset, mom);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_step(tpf_ctx* c, bool anyS, int mode, int ntiles, int offset, double* mom) {
-    if (ntiles <= 0) return hipSuccess;
-    const int code = c->tile_code;
+template <typename T, int MODE>
+static hipError_t launch_group(tpf_ctx* c, bool S, int t0, int n, int offset, double* mom) {
+    if (n <= 0) return hipSuccess;
+    return S ? launch_step_shape<T, true, MODE>(c, c->tile_code, t0, n, offset, mom)
+             : launch_step_shape<T, false, MODE>(c, c->tile_code, t0, n, offset, mom);
+}
+
+// Launches the step (or moments) kernel over a tile table whose first n_noS
+// tiles belong to domains without S and the rest to domains with S.
+static hipError_t launch_step(tpf_ctx* c, int mode, int ntiles, int n_noS, int offset, double* mom) {
+    hipError_t e;
     if (c->precision == 32) {
-        if (mode == kModeStep)
-            return anyS ? launch_step_shape<float, true, kModeStep>(c, code, ntiles, offset, mom)
-                        : launch_step_shape<float, false, kModeStep>(c, code, ntiles, offset, mom);
-        return anyS ? launch_step_shape<float, true, kModeMoments>(c, code, ntiles, offset, mom)
-                    : launch_step_shape<float, false, kModeMoments>(c, code, ntiles, offset, mom);
+        if (mode == kModeStep) {
+            if ((e = launch_group<float, kModeStep>(c, false, 0, n_noS, offset, mom))) return e;
+            return launch_group<float, kModeStep>(c, true, n_noS, ntiles - n_noS, offset, mom);
+        }
+        if ((e = launch_group<float, kModeMoments>(c, false, 0, n_noS, offset, mom))) return e;
+        return launch_group<float, kModeMoments>(c, true, n_noS, ntiles - n_noS, offset, mom);
     }
-    if (mode == kModeStep)
-        return anyS ? launch_step_shape<double, true, kModeStep>(c, code, ntiles, offset, mom)
-                    : launch_step_shape<double, false, kModeStep>(c, code, ntiles, offset, mom);
-    return anyS ? launch_step_shape<double, true, kModeMoments>(c, code, ntiles, offset, mom)
-                : launch_step_shape<double, false, kModeMoments>(c, code, ntiles, offset, mom);
+    if (mode == kModeStep) {
+        if ((e = launch_group<double, kModeStep>(c, false, 0, n_noS, offset, mom))) return e;
+        return launch_group<double, kModeStep>(c, true, n_noS, ntiles - n_noS, offset, mom);
+    }
+    if ((e = launch_group<double, kModeMoments>(c, false, 0, n_noS, offset, mom))) return e;
+    return launch_group<double, kModeMoments>(c, true, n_noS, ntiles - n_noS, offset, mom);
 }
 
 // Host -> device upload of all descriptors (small; issued on the stream).
@@ -318,15 +344,24 @@ static int upload_descriptors(tpf_ctx* c) {
     return TPF_OK;
 }
 
-// Tile table for a set of domains (all live ones, or one for moments).
-static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<int4>& out) {
+// Tile table for a set of domains (all live ones, or one for moments):
+// tiles of domains without the flux S first, then those with S, so each
+// group runs the kernel instance of its own kind.
+static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<int4>& out,
+                       int* n_noS = nullptr) {
     const TileShape* ts = find_tile(c->tile_code);
     out.clear();
-    for (int di : which) {
-        const auto& h = c->doms[di];
-        for (int y = 0; y < h.p.ny; y += ts->ty)
-            for (int x = 0; x < h.p.nx; x += ts->tx) out.push_back(make_int4(di, x, y, 0));
+    int split = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int di : which) {
+            const auto& h = c->doms[di];
+            if ((h.dev.has_s != 0) != (pass == 1)) continue;
+            for (int y = 0; y < h.p.ny; y += ts->ty)
+                for (int x = 0; x < h.p.nx; x += ts->tx) out.push_back(make_int4(di, x, y, 0));
+        }
+        if (pass == 0) split = (int)out.size();
     }
+    if (n_noS) *n_noS = split;
     if (out.size() > c->max_tiles) return TPF_EINVAL;
     if (!out.empty())
         HIP_OK(hipMemcpyAsync(c->d_tiles, out.data(), out.size() * sizeof(int4),
@@ -335,19 +370,13 @@ static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<in
     return TPF_OK;
 }
 
-static bool any_s(const tpf_ctx* c, const std::vector<int>& which) {
-    for (int di : which)
-        if (c->doms[di].dev.has_s) return true;
-    return false;
-}
-
 static int refresh_live(tpf_ctx* c) {
     std::vector<int> live;
     for (size_t i = 0; i < c->doms.size(); ++i)
         if (c->doms[i].status == TPF_OK) live.push_back((int)i);
     if (live != c->live_list || c->tiles_dirty || c->tiles_code_built != c->tile_code) {
         c->live_list = live;
-        int rc = build_tiles(c, live, c->tiles);
+        int rc = build_tiles(c, live, c->tiles, &c->tiles_noS);
         if (rc) return rc;
         c->tiles_code_built = c->tile_code;
         c->tiles_dirty = false;
@@ -370,8 +399,8 @@ static int run_steps(tpf_ctx* c, int64_t n) {
         if (c->doms[i].status != TPF_OK) c->doms[i].dev.live = 0;
     rc = upload_descriptors(c);
     if (rc) return rc;
-    const bool S = any_s(c, c->live_list);
     const int ntiles = (int)c->tiles.size();
+    const int nnoS = c->tiles_noS;
     for (int64_t s = 0; s < n; ++s) {
         const int off = (int)(s & 1);
         if (c->timing) {
@@ -379,12 +408,12 @@ static int run_steps(tpf_ctx* c, int64_t n) {
             HIP_OK(hipEventCreate(&a));
             HIP_OK(hipEventCreate(&b));
             HIP_OK(hipEventRecord(a, c->stream));
-            HIP_OK(launch_step(c, S, kModeStep, ntiles, off, nullptr));
+            HIP_OK(launch_step(c, kModeStep, ntiles, nnoS, off, nullptr));
             HIP_OK(hipEventRecord(b, c->stream));
             c->ev_pool.push_back(a);
             c->ev_pool.push_back(b);
         } else {
-            HIP_OK(launch_step(c, S, kModeStep, ntiles, off, nullptr));
+            HIP_OK(launch_step(c, kModeStep, ntiles, nnoS, off, nullptr));
         }
     }
     for (int di : c->live_list) {
@@ -400,7 +429,10 @@ static int reduce(tpf_ctx* c, const std::vector<int>& which, bool update_snap) {
     if (which.empty()) return TPF_OK;
     HIP_OK(hipMemcpyAsync(c->d_domlist, which.data(), which.size() * sizeof(int),
                           hipMemcpyHostToDevice, c->stream));
-    dim3 grid(kRedBlocks, (unsigned)which.size());
+    int maxny = 1;
+    for (int di : which) maxny = std::max(maxny, c->doms[di].p.ny);
+    const int nblk = std::min(kRedMaxBlocks, maxny);
+    dim3 grid(nblk, (unsigned)which.size());
     if (c->precision == 32)
         hipLaunchKernelGGL(reduce_partials<float>, grid, dim3(kRedThreads), 0, c->stream, c->d_doms,
                            c->d_domlist, update_snap ? 1 : 0, c->d_partials);
@@ -409,7 +441,7 @@ static int reduce(tpf_ctx* c, const std::vector<int>& which, bool update_snap) {
                            c->d_domlist, update_snap ? 1 : 0, c->d_partials);
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(reduce_final, dim3((which.size() + 63) / 64), dim3(64), 0, c->stream,
-                       c->d_domlist, (int)which.size(), c->d_partials, c->d_red);
+                       c->d_domlist, (int)which.size(), nblk, c->d_partials, c->d_red);
     HIP_OK(hipGetLastError());
     std::vector<double> red(4 * c->doms.size());
     HIP_OK(hipMemcpyAsync(red.data(), c->d_red, red.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -547,7 +579,7 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
     c->d_doms = (DomDev*)take(nd * sizeof(DomDev));
     c->d_tiles = (int4*)take(c->max_tiles * sizeof(int4));
     c->d_domlist = (int*)take(nd * sizeof(int));
-    c->d_partials = (double*)take(nd * kRedBlocks * 7 * sizeof(double));
+    c->d_partials = (double*)take(nd * kRedMaxBlocks * 7 * sizeof(double));
     c->d_red = (double*)take(nd * 4 * sizeof(double));
     c->d_scratch = (double*)take(18 * max_nodes(c) * sizeof(double));
     if (off > need) return TPF_EINVAL;
@@ -624,11 +656,11 @@ extern "C" int tpf_read_moments(tpf_ctx* c, int32_t id, double* phi1, double* ux
     const size_t N = (size_t)h.p.nx * h.p.ny;
     std::vector<int4> t;
     std::vector<int> one = {id};
-    int rc = build_tiles(c, one, t);
+    int nnoS = 0;
+    int rc = build_tiles(c, one, t, &nnoS);
     if (rc) return rc;
     c->tiles_dirty = true;
-    const bool S = h.dev.has_s != 0;
-    HIP_OK(launch_step(c, S, kModeMoments, (int)t.size(), 0, c->d_scratch));
+    HIP_OK(launch_step(c, kModeMoments, (int)t.size(), nnoS, 0, c->d_scratch));
     std::vector<double> buf(4 * N);
     HIP_OK(hipMemcpyAsync(buf.data(), c->d_scratch, 4 * N * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));

@@ -55,8 +55,11 @@ struct DomDev {
 // are clamped so that every access stays inside the domain.
 __device__ __forceinline__ int map_index(int j, int n, int periodic) {
     if (periodic) {
-        j %= n;
-        return j < 0 ? j + n : j;
+        if ((unsigned)j >= (unsigned)n) {
+            j %= n;
+            if (j < 0) j += n;
+        }
+        return j;
     }
     if (j < 0) j = -1 - j;
     else if (j >= n) j = 2 * n - 1 - j;

@@ -28,6 +28,167 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return start + (b >> 3);
 }
 
+// Per-node part of the step, shared by the tile and strip kernels: given the
+// stencil values of phi0, phi1, mubar1 (and psi), the pulled populations and
+// the lagged fields of the node, forms the forces, u, p and writes either the
+// post-collision populations and lagged fields or the moments.
+template <typename T, int MODE>
+__device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, int N, T ph0, T ph1,
+                                            T gx0, T gy0, T lap0, T gx1, T gy1, T lap1, T mub,
+                                            T gmx, T gmy, T dpsix, T dpsiy, T (&fp)[9], T (&gp)[9],
+                                            T lAx, T lAy, T lB, T lCxx, T lCyy, T lCxy, int cur,
+                                            double* __restrict__ mom_out) {
+    const T c2 = T(d.c2);
+    T mu0, mu1, mu2;
+    (void)mubar1<T>(d, ph0, ph1, lap0, lap1, mu0, mu1, mu2);
+
+    // degenerate mobility, 2f1s form f = phi1 (1 - phi1)(1 - phi0) (Sec. 4)
+    const T fdeg = ph1 * (T(1) - ph1) * (T(1) - ph0);
+    const T a = T(d.Mdeg_frac) * (T(1) - fdeg);
+
+    // density, viscosity (linear in phi_p), grad(rho)
+    const T ph2 = T(1) - ph0 - ph1;
+    const T rho = T(d.rho0) * ph0 + T(d.rho1) * ph1 + T(d.rho2) * ph2;
+    const T muv = T(d.muv0) * ph0 + T(d.muv1) * ph1 + T(d.muv2) * ph2;
+    const T drx = T(d.drho0) * gx0 + T(d.drho1) * gx1;
+    const T dry = T(d.drho0) * gy0 + T(d.drho1) * gy1;
+
+    // surface tension F_s = sum_p mu_p grad(phi_p)
+    T Fx = mu0 * gx0 + mu1 * gx1 + mu2 * (-gx0 - gx1);
+    T Fy = mu0 * gy0 + mu1 * gy1 + mu2 * (-gy0 - gy1);
+    T Sx = T(0), Sy = T(0);
+    if (dS) {
+        // S = (rho1 - rho2) M grad(mubar1)/gamma1; F_c from the previous psi
+        const T Mob = T(d.Mcst) + T(d.Mdeg) * fdeg;
+        Sx = T(d.Sfac) * Mob * gmx;
+        Sy = T(d.Sfac) * Mob * gmy;
+        Fx += T(-0.5) * dpsiy;
+        Fy += T(0.5) * dpsix;
+    }
+    Fx += T(d.Fbx);
+    Fy += T(d.Fby);
+
+    // NS moments; velocity with the solid correction (Sec. 3)
+    T mg[9];
+    nat_moments(gp, mg);
+    const T inv_rho = T(1) / rho;
+    const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
+    const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
+    const T fsx = T(d.uwx) - usx, fsy = T(d.uwy) - usy;
+    const T ux = usx + T(0.5) * ph0 * fsx;
+    const T uy = usy + T(0.5) * ph0 * fsy;
+
+    // per-node NS rates from mu/(rho (1 - phi0)) (Sec. 3)
+    const T om = T(1) - ph0;
+    const T s2a = om / (muv * inv_rho / T(d.cfa) + T(0.5) * om);
+    const T s2b = om / (muv * inv_rho / T(d.cfb) + T(0.5) * om);
+
+    // pressure (Sec. 3, 2D constants)
+    const T Q = ux * drx + uy * dry;
+    const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
+    const T H = T(d.Kp) * (T(d.AH) - (d.BH == 0.0 ? T(0) : T(d.BH) / s2a));
+    const T p = T(d.pfac) * ((mg[0] - gp[0]) + (T(0.5) + H) * Q - T(d.pw) * Bn +
+                             T(0.5) * T(d.Kp) * (Bn - lB));
+
+    if constexpr (MODE == kModeMoments) {
+        mom_out[id] = double(ph1);
+        mom_out[N + id] = double(ux);
+        mom_out[2 * N + id] = double(uy);
+        mom_out[3 * N + id] = double(p);
+        return;
+    }
+    T* __restrict__ fout = (T*)d.f[cur ^ 1];
+    T* __restrict__ gout = (T*)d.g[cur ^ 1];
+
+    // ---- CH collision in Hermite space ----
+    {
+        T m[9], h[9];
+        nat_moments(fp, m);
+        to_hermite(m, h, c2);
+        const T Ax = ph1 * ux, Ay = ph1 * uy;
+        const T emu = T(d.eta) * mub;
+        // d_t(phi u) by explicit Euler, plus the degenerate-mobility correction
+        const T Wx = (Ax - lAx) + a * T(d.eta) * c2 * gmx;
+        const T Wy = (Ay - lAy) + a * T(d.eta) * c2 * gmy;
+        const T s0 = T(d.sphi[0]), s1 = T(d.sphi[1]), s2 = T(d.sphi[2]);
+        const T s3 = T(d.sphi[3]), s4 = T(d.sphi[4]);
+        const T e3 = c2 * (emu - ph1);
+        h[0] = h[0] - s0 * (h[0] - ph1);
+        h[1] = h[1] - s1 * (h[1] - Ax) + (T(1) - T(0.5) * s1) * Wx;
+        h[2] = h[2] - s1 * (h[2] - Ay) + (T(1) - T(0.5) * s1) * Wy;
+        h[3] = h[3] - s2 * (h[3] - e3);
+        h[4] = h[4] - s2 * (h[4] - e3);
+        h[5] = h[5] - s2 * h[5];
+        h[6] = h[6] - s3 * h[6];
+        h[7] = h[7] - s3 * h[7];
+        h[8] = h[8] - s4 * (h[8] - c2 * c2 * (ph1 - emu));
+        T fo[9];
+        from_hermite(h, fo, c2);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(fo[q], &fout[q * N + id]);
+        T* lagA = (T*)d.lagA;
+        lagA[id] = Ax;
+        lagA[N + id] = Ay;
+    }
+
+    // ---- NS collision in Hermite space ----
+    {
+        const T Gx = Fx + ph0 * rho * fsx, Gy = Fy + ph0 * rho * fsy;
+        const T Jx = rho * ux, Jy = rho * uy;
+        const T Pxx = rho * ux * ux - Sx * ux;
+        const T Pyy = rho * uy * uy - Sy * uy;
+        const T Pxy = rho * ux * uy - T(0.5) * (Sx * uy + ux * Sy);
+        // M2F = uF + Fu - d_t((Su + uS)/2) + c_s^2 (u grad rho + grad rho u)
+        //       + (1 - 3 c_s^2)(u . grad rho) I
+        T Cxx = T(0), Cyy = T(0), Cxy = T(0), dCxx = T(0), dCyy = T(0), dCxy = T(0);
+        if (dS) {
+            Cxx = Sx * ux;
+            Cyy = Sy * uy;
+            Cxy = T(0.5) * (Sx * uy + Sy * ux);
+            dCxx = Cxx - lCxx;
+            dCyy = Cyy - lCyy;
+            dCxy = Cxy - lCxy;
+        }
+        const T q3 = (T(1) - T(3) * c2) * Q;
+        const T Mxx = T(2) * ux * Fx - dCxx + T(2) * c2 * ux * drx + q3;
+        const T Myy = T(2) * uy * Fy - dCyy + T(2) * c2 * uy * dry + q3;
+        const T Mxy = ux * Fy + Fx * uy - dCxy + c2 * (ux * dry + drx * uy);
+        T h[9];
+        to_hermite(mg, h, c2);
+        const T gauge = T(d.gauge);
+        const T sg0 = T(d.sg0), sg1 = T(d.sg1), sg3 = T(d.sg3), sg4 = T(d.sg4);
+        h[0] = h[0] - sg0 * (h[0] - gauge) + (T(1) - T(0.5) * sg0) * Q;
+        h[1] = h[1] - sg1 * (h[1] - Jx) + (T(1) - T(0.5) * sg1) * Gx;
+        h[2] = h[2] - sg1 * (h[2] - Jy) + (T(1) - T(0.5) * sg1) * Gy;
+        h[3] = h[3] - s2a * (h[3] - (p + Pxx - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Mxx;
+        h[4] = h[4] - s2a * (h[4] - (p + Pyy - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Myy;
+        h[5] = h[5] - s2b * (h[5] - Pxy) + (T(1) - T(0.5) * s2b) * Mxy;
+        h[6] = h[6] - sg3 * h[6];
+        h[7] = h[7] - sg3 * h[7];
+        h[8] = h[8] - sg4 * (h[8] - (c2 * c2 * gauge - c2 * p));
+        T go[9];
+        from_hermite(h, go, c2);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(go[q], &gout[q * N + id]);
+        ((T*)d.lagB)[id] = Bn;
+        if (dS) {
+            T* lagC = (T*)d.lagC;
+            lagC[id] = Cxx;
+            lagC[N + id] = Cyy;
+            lagC[2 * N + id] = Cxy;
+            ((T*)d.psi[cur ^ 1])[id] = Sx * uy - Sy * ux;
+        }
+    }
+}
+
+// Pulled populations of both lattices at node (x, y).
+template <typename T>
+__device__ __forceinline__ void pull9(const T* __restrict__ fin, int x, int y, int nx, int ny, int px,
+                                      int py, int N, T (&out)[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = pull(fin, q, x, y, nx, ny, px, py, N);
+}
+
 template <typename T, int TX, int TY, int NT, bool HAS_S, int MODE>
 __global__ void __launch_bounds__(NT)
 step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
@@ -86,14 +247,9 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
     __syncthreads();
 
     // ---- 3. per-node macroscopic fields and collisions ----
-    const T c2 = T(d.c2);
-    T* __restrict__ fout = (T*)d.f[cur ^ 1];
-    T* __restrict__ gout = (T*)d.g[cur ^ 1];
-    T* __restrict__ lagA = (T*)d.lagA;
-    T* __restrict__ lagB = (T*)d.lagB;
-    T* __restrict__ lagC = (T*)d.lagC;
-    T* __restrict__ psi_out = dS ? (T*)d.psi[cur ^ 1] : nullptr;
-
+    const T* __restrict__ lagA = (const T*)d.lagA;
+    const T* __restrict__ lagB = (const T*)d.lagB;
+    const T* __restrict__ lagC = (const T*)d.lagC;
     for (int k = tid; k < TX * TY; k += NT) {
         const int lx = k % TX, ly = k / TX;
         const int x = x0 + lx, y = y0 + ly;
@@ -101,158 +257,187 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         const int id = y * nx + x;
         const int ip = (ly + 2) * WX + (lx + 2);
         const int iv = (ly + 1) * VX + (lx + 1);
-
-        // phase fields and their stencils
-        const T ph0 = s_phi0[ip], ph1 = s_phi1[ip];
-        T gx0, gy0, lap0, gx1, gy1, lap1;
+        T gx0, gy0, lap0, gx1, gy1, lap1, gmx, gmy, dpx = T(0), dpy = T(0);
         stencil9(s_phi0, ip, WX, gx0, gy0, lap0);
         stencil9(s_phi1, ip, WX, gx1, gy1, lap1);
-        T mu0, mu1, mu2;
-        (void)mubar1<T>(d, ph0, ph1, lap0, lap1, mu0, mu1, mu2);
-        const T mub = s_mub[iv];
-        T gmx, gmy;
         grad9(s_mub, iv, VX, gmx, gmy);
-
-        // degenerate mobility, 2f1s form f = phi1 (1 - phi1)(1 - phi0) (Sec. 4)
-        const T fdeg = ph1 * (T(1) - ph1) * (T(1) - ph0);
-        const T a = T(d.Mdeg_frac) * (T(1) - fdeg);
-
-        // density, viscosity (linear in phi_p), grad(rho)
-        const T ph2 = T(1) - ph0 - ph1;
-        const T rho = T(d.rho0) * ph0 + T(d.rho1) * ph1 + T(d.rho2) * ph2;
-        const T muv = T(d.muv0) * ph0 + T(d.muv1) * ph1 + T(d.muv2) * ph2;
-        const T drx = T(d.drho0) * gx0 + T(d.drho1) * gx1;
-        const T dry = T(d.drho0) * gy0 + T(d.drho1) * gy1;
-
-        // surface tension F_s = sum_p mu_p grad(phi_p)
-        T Fx = mu0 * gx0 + mu1 * gx1 + mu2 * (-gx0 - gx1);
-        T Fy = mu0 * gy0 + mu1 * gy1 + mu2 * (-gy0 - gy1);
-        T Sx = T(0), Sy = T(0);
+        T lCxx = T(0), lCyy = T(0), lCxy = T(0);
         if (dS) {
-            // S = (rho1 - rho2) M grad(mubar1)/gamma1; F_c from the previous psi
-            const T Mob = T(d.Mcst) + T(d.Mdeg) * fdeg;
-            Sx = T(d.Sfac) * Mob * gmx;
-            Sy = T(d.Sfac) * Mob * gmy;
-            T dpx, dpy;
             grad9(s_psi, iv, VX, dpx, dpy);
-            Fx += T(-0.5) * dpy;
-            Fy += T(0.5) * dpx;
+            lCxx = lagC[id];
+            lCyy = lagC[N + id];
+            lCxy = lagC[2 * N + id];
         }
-        Fx += T(d.Fbx);
-        Fy += T(d.Fby);
+        T fp[9], gp[9];
+        pull9(gin, x, y, nx, ny, px, py, N, gp);
+        pull9(fin, x, y, nx, ny, px, py, N, fp);
+        node_update<T, MODE>(d, dS, id, N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
+                             s_mub[iv], gmx, gmy, dpx, dpy, fp, gp, lagA[id], lagA[N + id], lagB[id],
+                             lCxx, lCyy, lCxy, cur, mom_out);
+    }
+}
 
-        // NS populations, moments; velocity with the solid correction (Sec. 3)
-        T gp[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) gp[q] = pull(gin, q, x, y, nx, ny, px, py, N);
-        T mg[9];
-        nat_moments(gp, mg);
-        const T inv_rho = T(1) / rho;
-        const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
-        const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
-        const T fsx = T(d.uwx) - usx, fsy = T(d.uwy) - usy;
-        const T ux = usx + T(0.5) * ph0 * fsx;
-        const T uy = usy + T(0.5) * ph0 * fsy;
+// ---------------------------------------------------------------------------
+// Strip kernel: one wavefront per (domain, 64-column strip, CH-row chunk).
+// The wave marches down its chunk one row per iteration r:
+//   A. loads the pulled CH populations of row y0 - 2 + r for its 64 columns
+//      (kept in a 3-deep register ring) plus 4 halo columns, and writes
+//      phi0, phi1 of that row into a 5-row LDS ring;
+//   B. computes mubar1 (and stages psi) for the row above into a 3-row ring;
+//   C. updates the row two above, whose populations are in registers.
+// Each population is read once from memory apart from the 4 halo columns and
+// the 4 halo rows of each chunk, which neighbouring waves share through L2.
+// ---------------------------------------------------------------------------
+template <typename T, bool HAS_S>
+struct StripShared {
+    T phi0[5][68];
+    T phi1[5][68];
+    T mub[3][66];
+    T psi[HAS_S ? 3 : 1][66];
+};
 
-        // per-node NS rates from mu/(rho (1 - phi0)) (Sec. 3)
-        const T om = T(1) - ph0;
-        const T s2a = om / (muv * inv_rho / T(d.cfa) + T(0.5) * om);
-        const T s2b = om / (muv * inv_rho / T(d.cfb) + T(0.5) * om);
+template <typename T, int CH, bool HAS_S, int MODE>
+__device__ __forceinline__ void strip_iter(const DomDev& d, StripShared<T, HAS_S>& sh, int r, int x0,
+                                           int y0, int lane, int cur, bool dS, T (&fL)[9], T (&fU)[9],
+                                           double* __restrict__ mom_out) {
+    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
+    const int N = nx * ny;
+    const T* __restrict__ fin = (const T*)d.f[cur];
+    const T* __restrict__ phi0 = (const T*)d.phi0;
+    const int yr = y0 - 2 + r;          // phi row loaded in this iteration
+    const int yu = yr - 2;              // row updated in this iteration
+    const int x = x0 + lane;
+    const bool do_update = (r >= 4) && (yu < ny) && (x < nx);
 
-        // pressure (Sec. 3, 2D constants)
-        const T Q = ux * drx + uy * dry;
-        const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
-        const T Bp = lagB[id];
-        const T H = T(d.Kp) * (T(d.AH) - (d.BH == 0.0 ? T(0) : T(d.BH) / s2a));
-        const T p = T(d.pfac) * ((mg[0] - gp[0]) + (T(0.5) + H) * Q - T(d.pw) * Bn +
-                                 T(0.5) * T(d.Kp) * (Bn - Bp));
-
-        if constexpr (MODE == kModeMoments) {
-            mom_out[id] = double(ph1);
-            mom_out[N + id] = double(ux);
-            mom_out[2 * N + id] = double(uy);
-            mom_out[3 * N + id] = double(p);
-            continue;
+    // prefetch the NS populations and lagged fields of the row to update
+    T gp[9];
+    T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
+    int idu = 0;
+    if (do_update) {
+        idu = yu * nx + x;
+        pull9((const T*)d.g[cur], x, yu, nx, ny, px, py, N, gp);
+        lAx = ((const T*)d.lagA)[idu];
+        lAy = ((const T*)d.lagA)[N + idu];
+        lB = ((const T*)d.lagB)[idu];
+        if (dS) {
+            lCxx = ((const T*)d.lagC)[idu];
+            lCyy = ((const T*)d.lagC)[N + idu];
+            lCxy = ((const T*)d.lagC)[2 * N + idu];
         }
+    }
 
-        // ---- CH collision in Hermite space ----
-        {
-            T fp[9];
+    // A. phi0, phi1 of row yr (own column + lanes 0..3 for the 4 halo columns)
+    const int slot5 = r % 5;
+    {
+        const int sy = map_index(yr, ny, py);
+        const int sx = map_index(x, nx, px);
+        pull9(fin, sx, sy, nx, ny, px, py, N, fL);
+        T s = fL[0];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) fp[q] = pull(fin, q, x, y, nx, ny, px, py, N);
-            T m[9], h[9];
-            nat_moments(fp, m);
-            to_hermite(m, h, c2);
-            const T Ax = ph1 * ux, Ay = ph1 * uy;
-            const T emu = T(d.eta) * mub;
-            // d_t(phi u) by explicit Euler, plus the degenerate-mobility correction
-            const T Wx = (Ax - lagA[id]) + a * T(d.eta) * c2 * gmx;
-            const T Wy = (Ay - lagA[N + id]) + a * T(d.eta) * c2 * gmy;
-            const T s0 = T(d.sphi[0]), s1 = T(d.sphi[1]), s2 = T(d.sphi[2]);
-            const T s3 = T(d.sphi[3]), s4 = T(d.sphi[4]);
-            const T e3 = c2 * (emu - ph1);
-            h[0] = h[0] - s0 * (h[0] - ph1);
-            h[1] = h[1] - s1 * (h[1] - Ax) + (T(1) - T(0.5) * s1) * Wx;
-            h[2] = h[2] - s1 * (h[2] - Ay) + (T(1) - T(0.5) * s1) * Wy;
-            h[3] = h[3] - s2 * (h[3] - e3);
-            h[4] = h[4] - s2 * (h[4] - e3);
-            h[5] = h[5] - s2 * h[5];
-            h[6] = h[6] - s3 * h[6];
-            h[7] = h[7] - s3 * h[7];
-            h[8] = h[8] - s4 * (h[8] - c2 * c2 * (ph1 - emu));
-            from_hermite(h, fp, c2);
+        for (int q = 1; q < 9; ++q) s += fL[q];
+        sh.phi1[slot5][lane + 2] = s;
+        sh.phi0[slot5][lane + 2] = phi0[sy * nx + sx];
+        if (lane < 4) {
+            const int cx = lane < 2 ? lane : 64 + lane;   // cells 0, 1, 66, 67
+            const int hx = map_index(x0 - 2 + cx, nx, px);
+            T t = pull(fin, 0, hx, sy, nx, ny, px, py, N);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) fout[q * N + id] = fp[q];
-            lagA[id] = Ax;
-            lagA[N + id] = Ay;
+            for (int q = 1; q < 9; ++q) t += pull(fin, q, hx, sy, nx, ny, px, py, N);
+            sh.phi1[slot5][cx] = t;
+            sh.phi0[slot5][cx] = phi0[sy * nx + hx];
         }
+    }
+    __syncthreads();
 
-        // ---- NS collision in Hermite space ----
-        {
-            const T Gx = Fx + ph0 * rho * fsx, Gy = Fy + ph0 * rho * fsy;
-            const T Jx = rho * ux, Jy = rho * uy;
-            const T Pxx = rho * ux * ux - Sx * ux;
-            const T Pyy = rho * uy * uy - Sy * uy;
-            const T Pxy = rho * ux * uy - T(0.5) * (Sx * uy + ux * Sy);
-            // M2F = uF + Fu - d_t((Su + uS)/2) + c_s^2 (u grad rho + grad rho u)
-            //       + (1 - 3 c_s^2)(u . grad rho) I
-            T Cxx = T(0), Cyy = T(0), Cxy = T(0), dCxx = T(0), dCyy = T(0), dCxy = T(0);
-            if (dS) {
-                Cxx = Sx * ux;
-                Cyy = Sy * uy;
-                Cxy = T(0.5) * (Sx * uy + Sy * ux);
-                dCxx = Cxx - lagC[id];
-                dCyy = Cyy - lagC[N + id];
-                dCxy = Cxy - lagC[2 * N + id];
-            }
-            const T q3 = (T(1) - T(3) * c2) * Q;
-            const T Mxx = T(2) * ux * Fx - dCxx + T(2) * c2 * ux * drx + q3;
-            const T Myy = T(2) * uy * Fy - dCyy + T(2) * c2 * uy * dry + q3;
-            const T Mxy = ux * Fy + Fx * uy - dCxy + c2 * (ux * dry + drx * uy);
-            T h[9];
-            to_hermite(mg, h, c2);
-            const T gauge = T(d.gauge);
-            const T sg0 = T(d.sg0), sg1 = T(d.sg1), sg3 = T(d.sg3), sg4 = T(d.sg4);
-            h[0] = h[0] - sg0 * (h[0] - gauge) + (T(1) - T(0.5) * sg0) * Q;
-            h[1] = h[1] - sg1 * (h[1] - Jx) + (T(1) - T(0.5) * sg1) * Gx;
-            h[2] = h[2] - sg1 * (h[2] - Jy) + (T(1) - T(0.5) * sg1) * Gy;
-            h[3] = h[3] - s2a * (h[3] - (p + Pxx - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Mxx;
-            h[4] = h[4] - s2a * (h[4] - (p + Pyy - c2 * gauge)) + (T(1) - T(0.5) * s2a) * Myy;
-            h[5] = h[5] - s2b * (h[5] - Pxy) + (T(1) - T(0.5) * s2b) * Mxy;
-            h[6] = h[6] - sg3 * h[6];
-            h[7] = h[7] - sg3 * h[7];
-            h[8] = h[8] - sg4 * (h[8] - (c2 * c2 * gauge - c2 * p));
-            from_hermite(h, gp, c2);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) gout[q * N + id] = gp[q];
-            lagB[id] = Bn;
-            if (dS) {
-                lagC[id] = Cxx;
-                lagC[N + id] = Cyy;
-                lagC[2 * N + id] = Cxy;
-                psi_out[id] = Sx * uy - Sy * ux;
+    // B. mubar1 (and psi) of row yr - 1 on 66 cells (x0 - 1 .. x0 + 64)
+    const int slot3 = r % 3;
+    if (r >= 2) {
+        const T* pm = sh.phi1[(r + 3) % 5];  // row yr - 2
+        const T* p0 = sh.phi1[(r + 4) % 5];  // row yr - 1
+        const T* pp = sh.phi1[slot5];        // row yr
+        const T* qm = sh.phi0[(r + 3) % 5];
+        const T* q0 = sh.phi0[(r + 4) % 5];
+        const T* qp = sh.phi0[slot5];
+        for (int c = lane; c < 66; c += 64) {
+            const int i = c + 1;
+            const T l1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
+                          (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) / T(6);
+            const T l0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
+                          (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) / T(6);
+            T mu0, mu1, mu2;
+            sh.mub[slot3][c] = mubar1<T>(d, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
+            if constexpr (HAS_S) {
+                if (dS) {
+                    const int sx = map_index(x0 - 1 + c, nx, px);
+                    const int sy = map_index(yr - 1, ny, py);
+                    sh.psi[slot3][c] = ((const T*)d.psi[cur])[sy * nx + sx];
+                }
             }
         }
+    }
+    __syncthreads();
+
+    // C. update row yu = yr - 2 (phi rows yu-1..yu+1, mubar rows yu-1..yu+1)
+    if (do_update) {
+        const int i = lane + 2;   // phi cell of the node
+        const int j = lane + 1;   // mubar cell of the node
+        const T* pm = sh.phi1[(r + 2) % 5];  // row yu - 1
+        const T* p0 = sh.phi1[(r + 3) % 5];  // row yu
+        const T* pp = sh.phi1[(r + 4) % 5];  // row yu + 1
+        const T* qm = sh.phi0[(r + 2) % 5];
+        const T* q0 = sh.phi0[(r + 3) % 5];
+        const T* qp = sh.phi0[(r + 4) % 5];
+        const T* mm = sh.mub[(r + 1) % 3];   // row yu - 1
+        const T* m0 = sh.mub[(r + 2) % 3];   // row yu
+        const T* mp = sh.mub[slot3];         // row yu + 1
+        const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) / T(12);
+        const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) / T(12);
+        const T lap1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
+                        (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) / T(6);
+        const T gx0 = (T(4) * (q0[i + 1] - q0[i - 1]) + (qp[i + 1] - qp[i - 1] + qm[i + 1] - qm[i - 1])) / T(12);
+        const T gy0 = (T(4) * (qp[i] - qm[i]) + (qp[i + 1] - qm[i + 1] + qp[i - 1] - qm[i - 1])) / T(12);
+        const T lap0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
+                        (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) / T(6);
+        const T gmx = (T(4) * (m0[j + 1] - m0[j - 1]) + (mp[j + 1] - mp[j - 1] + mm[j + 1] - mm[j - 1])) / T(12);
+        const T gmy = (T(4) * (mp[j] - mm[j]) + (mp[j + 1] - mm[j + 1] + mp[j - 1] - mm[j - 1])) / T(12);
+        T dpx = T(0), dpy = T(0);
+        if constexpr (HAS_S) {
+            if (dS) {
+                const T* sm = sh.psi[(r + 1) % 3];
+                const T* s0 = sh.psi[(r + 2) % 3];
+                const T* sp = sh.psi[slot3];
+                dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) / T(12);
+                dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) / T(12);
+            }
+        }
+        node_update<T, MODE>(d, dS, idu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
+                             gmy, dpx, dpy, fU, gp, lAx, lAy, lB, lCxx, lCyy, lCxy, cur, mom_out);
+    }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE>
+__global__ void __launch_bounds__(64)
+strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+             int step_offset, double* __restrict__ mom_out) {
+    __shared__ StripShared<T, HAS_S> sh;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int4 tile = tiles[t];
+    const DomDev& d = doms[tile.x];
+    if (!d.live && MODE == kModeStep) return;
+    const int cur = (d.parity + step_offset) & 1;
+    const bool dS = HAS_S && d.has_s;
+    const int lane = threadIdx.x;
+    T F0[9], F1[9], F2[9];
+    // row ring: iteration r loads into F[r % 3] and updates with F[(r + 1) % 3]
+    // (the row loaded two iterations earlier)
+    constexpr int R = CH + 4;
+    for (int r = 0; r < R; r += 3) {
+        strip_iter<T, CH, HAS_S, MODE>(d, sh, r, tile.y, tile.z, lane, cur, dS, F0, F1, mom_out);
+        if (r + 1 < R)
+            strip_iter<T, CH, HAS_S, MODE>(d, sh, r + 1, tile.y, tile.z, lane, cur, dS, F1, F2, mom_out);
+        if (r + 2 < R)
+            strip_iter<T, CH, HAS_S, MODE>(d, sh, r + 2, tile.y, tile.z, lane, cur, dS, F2, F0, mom_out);
     }
 }
 
@@ -323,12 +508,13 @@ __device__ __forceinline__ void csum_merge(CSum& a, const CSum& b) {
     a.c += b.c;
 }
 
-constexpr int kRedBlocks = 64;   // partial-sum blocks per domain
+constexpr int kRedMaxBlocks = 256;  // partial-sum blocks per domain (upper bound)
 constexpr int kRedThreads = 256;
 
-// Per domain (blockIdx.y), per node: phi1 = sum of the pulled CH populations;
-// accumulates sum phi1, sum (phi1 - snap)^2, sum phi1^2, a non-finite count,
-// and (when update_snap) stores phi1 into snap.  partials: [dom][block][7].
+// Per domain (blockIdx.y), rows y = blockIdx.x + k gridDim.x, columns by
+// thread: phi1 = sum of the pulled CH populations; accumulates sum phi1,
+// sum (phi1 - snap)^2, sum phi1^2 and a non-finite count, and (when
+// update_snap) stores phi1 into snap.  partials: [dom][gridDim.x][7].
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_list, int update_snap,
@@ -339,18 +525,20 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
     const T* fin = (const T*)d.f[d.parity];
     CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
     double bad = 0.0;
-    for (int id = blockIdx.x * kRedThreads + threadIdx.x; id < N; id += kRedBlocks * kRedThreads) {
-        const int x = id % nx, y = id / nx;
-        T s = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
+    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+        for (int x = threadIdx.x; x < nx; x += kRedThreads) {
+            const int id = y * nx + x;
+            T s = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) s += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
-        const double v = double(s);
-        if (!isfinite(v)) bad += 1.0;
-        csum_add(m, v);
-        csum_add(n2, v * v);
-        const double prev = d.snap[id];
-        if (isfinite(prev)) csum_add(r, (v - prev) * (v - prev));
-        if (update_snap) d.snap[id] = v;
+            for (int q = 1; q < 9; ++q) s += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
+            const double v = double(s);
+            if (!isfinite(v)) bad += 1.0;
+            csum_add(m, v);
+            csum_add(n2, v * v);
+            const double prev = d.snap[id];
+            if (isfinite(prev)) csum_add(r, (v - prev) * (v - prev));
+            if (update_snap) d.snap[id] = v;
+        }
     }
     __shared__ double sh[7][kRedThreads];
     sh[0][threadIdx.x] = m.s; sh[1][threadIdx.x] = m.c;
@@ -373,19 +561,19 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
         __syncthreads();
     }
     if (threadIdx.x < 7)
-        partials[((size_t)blockIdx.y * kRedBlocks + blockIdx.x) * 7 + threadIdx.x] = sh[threadIdx.x][0];
+        partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 7 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // One thread per domain: folds the partials in a fixed order.
 // out: [dom][4] = mass, sum (phi1 - snap)^2, sum phi1^2, non-finite count.
-__global__ void reduce_final(const int* __restrict__ dom_list, int ndom, const double* __restrict__ partials,
-                             double* __restrict__ out) {
+__global__ void reduce_final(const int* __restrict__ dom_list, int ndom, int nblk,
+                             const double* __restrict__ partials, double* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ndom) return;
     CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
     double bad = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) {
-        const double* p = partials + ((size_t)j * kRedBlocks + b) * 7;
+    for (int b = 0; b < nblk; ++b) {
+        const double* p = partials + ((size_t)j * nblk + b) * 7;
         csum_merge(m, CSum{p[0], p[1]});
         csum_merge(r, CSum{p[2], p[3]});
         csum_merge(n2, CSum{p[4], p[5]});

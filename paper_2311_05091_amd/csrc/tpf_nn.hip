@@ -1,0 +1,639 @@
+// Kernels of the learned warm start (see include/tpf_nn.h): implicit-GEMM
+// 3x3 convolutions on the gfx950 BF16 matrix cores (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation), their weight and input gradients, and the elementwise
+// pieces of a small encoder-decoder (pooling, upsampling, concatenation,
+// output head with the MSE loss, Adam).
+//
+// Matrix-core operand layout (one wavefront, 16x16x32): lane l holds
+//   A: row l%16, k = 8*(l/16) .. 8*(l/16)+7      (8 bf16)
+//   B: col l%16, k = 8*(l/16) .. 8*(l/16)+7      (8 bf16)
+//   D: col l%16, rows 4*(l/16) .. 4*(l/16)+3      (4 fp32)
+// tpfnn_mfma_selftest checks it against a host product.
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "tpf_nn.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kOk = 0, kEinval = -1, kEdevice = -2;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+inline int launch_status() { return hipGetLastError() == hipSuccess ? kOk : kEdevice; }
+
+// ---------------------------------------------------------------------------
+// matrix-core layout self-test
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) mfma_selftest_k(const uint16_t* A, const uint16_t* B, float* D) {
+    const int l = threadIdx.x;
+    uint16_t a[8], b[8];
+    for (int e = 0; e < 8; ++e) {
+        a[e] = A[(l % 16) * 32 + 8 * (l / 16) + e];   // A[row][k], 16 x 32 row-major
+        b[e] = B[(8 * (l / 16) + e) * 16 + (l % 16)];  // B[k][col], 32 x 16 row-major
+    }
+    bf16x8 av = as_bf16x8(*(uint4*)a), bv = as_bf16x8(*(uint4*)b);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) D[(4 * (l / 16) + i) * 16 + (l % 16)] = acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, forward (also the input gradient with flipped weights)
+// GEMM: M = pixels (64 per block), N = output channels (BN per block),
+// K = 9 * Cin in chunks of 32 channels of one tap.
+// ---------------------------------------------------------------------------
+template <int BN>
+__global__ void __launch_bounds__(256)
+conv3x3_fwd_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint16_t* __restrict__ w,
+              const float* __restrict__ bias, int Cout, int relu, uint16_t* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[64][40];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][40];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int p0 = blockIdx.x * 64;
+    const int co0 = blockIdx.y * BN;
+    const int HW = H * W;
+    // loader roles
+    const int ar = tid >> 2, aseg = (tid & 3) * 8;
+    const int p = p0 + ar;
+    const int n = p / HW, rem = p - n * HW;
+    const int py = rem / W, px = rem - py * W;
+    const bool bload = tid < BN * 4;
+    const int bco = co0 + (tid >> 2), bseg = (tid & 3) * 8;
+
+    f32x4 acc[BN / 16];
+#pragma unroll
+    for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int kk = 0; kk < 9; ++kk) {
+        const int sy = py + kk / 3 - 1, sx = px + kk % 3 - 1;
+        const bool inb = (sy >= 0) && (sy < H) && (sx >= 0) && (sx < W);
+        const uint16_t* xr = x + ((size_t)(n * H + (inb ? sy : 0)) * W + (inb ? sx : 0)) * Cin;
+        const uint16_t* wr = w + ((size_t)bco * 9 + kk) * Cin;
+        for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
+            uint4 av = inb ? *(const uint4*)(xr + ci0 + aseg) : make_uint4(0, 0, 0, 0);
+            uint4 bv = bload ? *(const uint4*)(wr + ci0 + bseg) : make_uint4(0, 0, 0, 0);
+            __syncthreads();
+            *(uint4*)&As[ar][aseg] = av;
+            if (bload) *(uint4*)&Bs[tid >> 2][bseg] = bv;
+            __syncthreads();
+            const bf16x8 a = as_bf16x8(*(const uint4*)&As[16 * wave + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+            for (int j = 0; j < BN / 16; ++j) {
+                const bf16x8 b = as_bf16x8(*(const uint4*)&Bs[16 * j + (lane & 15)][(lane >> 4) * 8]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BN / 16; ++j) {
+        const int co = co0 + 16 * j + (lane & 15);
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * wave + 4 * (lane >> 4) + i;
+            float v = acc[j][i] + bb;
+            if (relu) v = v > 0.f ? v : 0.f;
+            y[(size_t)(p0 + row) * Cout + co] = f2bf(v);
+        }
+    }
+}
+
+__global__ void weight_flip_k(const uint16_t* __restrict__ w, int Cout, int Cin, uint16_t* __restrict__ wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)Cout * 9 * Cin;
+    if (i >= total) return;
+    // wt[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]
+    const int co = (int)(i % Cout);
+    const int64_t r = i / Cout;
+    const int kk = (int)(r % 9);
+    const int ci = (int)(r / 9);
+    wt[i] = w[((int64_t)co * 9 + (8 - kk)) * Cin + ci];
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, weight gradient (split over pixels, fixed-order reduction)
+// GEMM per tap: M = output channels (BM per block), N = 32 input channels,
+// K = pixels in chunks of 32.
+// ---------------------------------------------------------------------------
+template <int BM>
+__global__ void __launch_bounds__(256)
+conv3x3_wgrad_k(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy, int H, int W, int Cin,
+                int Cout, int P, int chunk, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][40];  // [co][pixel]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[32][40];  // [ci][pixel]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int co0 = blockIdx.x * BM;
+    const int ncb = Cin / 32;
+    const int kk = blockIdx.y / ncb, ci0 = (blockIdx.y % ncb) * 32;
+    const int dyk = kk / 3 - 1, dxk = kk % 3 - 1;
+    const int HW = H * W;
+    const int pbeg = blockIdx.z * chunk;
+    const int pend = min(P, pbeg + chunk);
+    // tiles: (BM/16) row groups of 16 channels x 2 column groups of 16 ci,
+    // spread over the 4 waves (each wave owns NCW column groups of one row group)
+    constexpr int RG = BM / 16, WPR = 4 / RG, NCW = 2 / WPR;
+    const int tr = wave % RG;
+    f32x4 acc[NCW];
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int pc = pbeg; pc < pend; pc += 32) {
+        // dy[p][co0 .. co0+BM) for 32 pixels: BM*32*2 bytes, 16 B per thread
+        uint4 av = make_uint4(0, 0, 0, 0);
+        const int apix = tid / (BM / 8), aseg = (tid % (BM / 8)) * 8;
+        const bool aload = tid < 32 * (BM / 8);
+        if (aload && pc + apix < pend) av = *(const uint4*)(dy + (size_t)(pc + apix) * Cout + co0 + aseg);
+        // x[p + tap][ci0 .. ci0+32) for 32 pixels
+        uint4 bv = make_uint4(0, 0, 0, 0);
+        const int bpix = tid >> 2, bseg = (tid & 3) * 8;
+        if (tid < 128 && pc + bpix < pend) {
+            const int p = pc + bpix;
+            const int n = p / HW, rem = p - n * HW;
+            const int sy = rem / W + dyk, sx = rem % W + dxk;
+            if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                bv = *(const uint4*)(x + ((size_t)(n * H + sy) * W + sx) * Cin + ci0 + bseg);
+        }
+        __syncthreads();
+        if (aload) {
+            const uint16_t* e = (const uint16_t*)&av;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[aseg + j][apix] = e[j];
+        }
+        if (tid < 128) {
+            const uint16_t* e = (const uint16_t*)&bv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[bseg + j][bpix] = e[j];
+        }
+        __syncthreads();
+        const bf16x8 a = as_bf16x8(*(const uint4*)&As[16 * tr + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int k = 0; k < NCW; ++k) {
+            const int tc = wave / RG + k * WPR;
+            const bf16x8 b = as_bf16x8(*(const uint4*)&Bs[16 * tc + (lane & 15)][(lane >> 4) * 8]);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+        }
+    }
+    float* out = part + (size_t)blockIdx.z * Cout * 9 * Cin;
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
+        const int tc = wave / RG + k * WPR;
+        const int ci = ci0 + 16 * tc + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = co0 + 16 * tr + 4 * (lane >> 4) + i;
+            out[((size_t)co * 9 + kk) * Cin + ci] = acc[k][i];
+        }
+    }
+}
+
+__global__ void sum_splits_k(const float* __restrict__ part, int splits, int64_t n, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+    out[i] = s;
+}
+
+// db partials: block b sums pixels [b*chunk, (b+1)*chunk) for every channel.
+__global__ void bias_grad_part_k(const uint16_t* __restrict__ dy, int P, int C, int chunk,
+                                 float* __restrict__ part) {
+    const int pbeg = blockIdx.x * chunk, pend = min(P, pbeg + chunk);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float s = 0.f;
+        for (int p = pbeg; p < pend; ++p) s += bf2f(dy[(size_t)p * C + c]);
+        part[(size_t)blockIdx.x * C + c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void relu_bwd_k(const uint16_t* __restrict__ y, uint16_t* __restrict__ dy, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(bf2f(y[i]) > 0.f)) dy[i] = 0;
+}
+
+__global__ void avgpool2_fwd_k(const uint16_t* __restrict__ x, int N, int H, int W, int C,
+                               uint16_t* __restrict__ y) {
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    int64_t r = i / C;
+    const int xo = (int)(r % Wo);
+    r /= Wo;
+    const int yo = (int)(r % Ho);
+    const int n = (int)(r / Ho);
+    const size_t b = ((size_t)(n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = bf2f(x[b]) + bf2f(x[b + C]) + bf2f(x[b + (size_t)W * C]) + bf2f(x[b + (size_t)W * C + C]);
+    y[i] = f2bf(0.25f * s);
+}
+
+__global__ void avgpool2_bwd_k(const uint16_t* __restrict__ dy, int N, int H, int W, int C,
+                               uint16_t* __restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * H * W * C) return;
+    const int c = (int)(i % C);
+    int64_t r = i / C;
+    const int xx = (int)(r % W);
+    r /= W;
+    const int yy = (int)(r % H);
+    const int n = (int)(r / H);
+    const int Ho = H / 2, Wo = W / 2;
+    dx[i] = f2bf(0.25f * bf2f(dy[((size_t)(n * Ho + yy / 2) * Wo + xx / 2) * C + c]));
+}
+
+__global__ void upsample2_fwd_k(const uint16_t* __restrict__ x, int N, int H, int W, int C,
+                                uint16_t* __restrict__ y) {
+    const int Ho = 2 * H, Wo = 2 * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    int64_t r = i / C;
+    const int xo = (int)(r % Wo);
+    r /= Wo;
+    const int yo = (int)(r % Ho);
+    const int n = (int)(r / Ho);
+    y[i] = x[((size_t)(n * H + yo / 2) * W + xo / 2) * C + c];
+}
+
+__global__ void upsample2_bwd_k(const uint16_t* __restrict__ dy, int N, int H, int W, int C,
+                                uint16_t* __restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * H * W * C) return;
+    const int c = (int)(i % C);
+    int64_t r = i / C;
+    const int xx = (int)(r % W);
+    r /= W;
+    const int yy = (int)(r % H);
+    const int n = (int)(r / H);
+    const int Wo = 2 * W;
+    const size_t b = ((size_t)(n * 2 * H + 2 * yy) * Wo + 2 * xx) * C + c;
+    const float s = bf2f(dy[b]) + bf2f(dy[b + C]) + bf2f(dy[b + (size_t)Wo * C]) +
+                    bf2f(dy[b + (size_t)Wo * C + C]);
+    dx[i] = f2bf(s);
+}
+
+__global__ void concat_k(const uint16_t* __restrict__ a, int Ca, const uint16_t* __restrict__ b, int Cb,
+                         int64_t npix, uint16_t* __restrict__ y) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C) return;
+    const int64_t p = i / C;
+    const int c = (int)(i % C);
+    y[i] = c < Ca ? a[p * Ca + c] : b[p * Cb + (c - Ca)];
+}
+
+__global__ void split_k(const uint16_t* __restrict__ dy, int Ca, int Cb, int64_t npix,
+                        uint16_t* __restrict__ da, uint16_t* __restrict__ db) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C) return;
+    const int64_t p = i / C;
+    const int c = (int)(i % C);
+    if (c < Ca) da[p * Ca + c] = dy[i];
+    else db[p * Cb + (c - Ca)] = dy[i];
+}
+
+__global__ void add_inplace_k(uint16_t* __restrict__ a, const uint16_t* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+}
+
+// Output head, one thread per pixel; per-block partial sums of dw, db, loss.
+constexpr int kHeadThreads = 256;
+
+__global__ void __launch_bounds__(kHeadThreads)
+head_k(const uint16_t* __restrict__ x, int64_t npix, int C, const float* __restrict__ w,
+       const float* __restrict__ b, float* __restrict__ pred, const float* __restrict__ target,
+       uint16_t* __restrict__ dx, double* __restrict__ part) {
+    __shared__ double red[kHeadThreads];
+    const int64_t p = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x;
+    const bool ok = p < npix;
+    float xv[32];
+    float z = b[0];
+    for (int c = 0; c < C; ++c) {
+        xv[c] = ok ? bf2f(x[p * C + c]) : 0.f;
+        z += w[c] * xv[c];
+    }
+    const float pr = 1.f / (1.f + __expf(-z));
+    if (ok) pred[p] = pr;
+    if (!target) return;
+    const float diff = ok ? pr - target[p] : 0.f;
+    const float dz = ok ? 2.f * diff * pr * (1.f - pr) / (float)npix : 0.f;
+    if (ok)
+        for (int c = 0; c < C; ++c) dx[p * C + c] = f2bf(dz * w[c]);
+    // C + 2 block sums: dw[0..C), db, loss
+    for (int k = 0; k < C + 2; ++k) {
+        double v = k < C ? (double)(dz * xv[k]) : (k == C ? (double)dz : (double)diff * diff);
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = kHeadThreads / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 2) + k] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void head_final_k(const double* __restrict__ part, int nblk, int C, int64_t npix,
+                             float* __restrict__ dw, float* __restrict__ db, double* __restrict__ loss) {
+    const int k = threadIdx.x;
+    if (k >= C + 2) return;
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[(size_t)i * (C + 2) + k];
+    if (k < C) dw[k] = (float)s;
+    else if (k == C) db[0] = (float)s;
+    else loss[0] = s / (double)npix;
+}
+
+__global__ void adam_k(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, uint16_t* __restrict__ pb, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+}
+
+__global__ void to_bf16_k(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ void from_bf16_k(const uint16_t* __restrict__ x, float* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = bf2f(x[i]);
+}
+
+__global__ void resample_k(const float* __restrict__ src, int N, int sh, int sw, float* __restrict__ dst,
+                           int dh, int dw) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * dh * dw) return;
+    const int x = (int)(i % dw);
+    const int64_t r = i / dw;
+    const int y = (int)(r % dh);
+    const int n = (int)(r / dh);
+    const float fy = dh > 1 ? (float)y * (float)(sh - 1) / (float)(dh - 1) : 0.f;
+    const float fx = dw > 1 ? (float)x * (float)(sw - 1) / (float)(dw - 1) : 0.f;
+    int y0 = (int)fy, x0 = (int)fx;
+    y0 = min(max(y0, 0), sh - 1);
+    x0 = min(max(x0, 0), sw - 1);
+    const int y1 = min(y0 + 1, sh - 1), x1 = min(x0 + 1, sw - 1);
+    const float ty = fy - (float)y0, tx = fx - (float)x0;
+    const float* s = src + (size_t)n * sh * sw;
+    const float v = (1.f - ty) * ((1.f - tx) * s[(size_t)y0 * sw + x0] + tx * s[(size_t)y0 * sw + x1]) +
+                    ty * ((1.f - tx) * s[(size_t)y1 * sw + x0] + tx * s[(size_t)y1 * sw + x1]);
+    dst[i] = v;
+}
+
+__global__ void pack_input_k(const float* __restrict__ phi0, const float* __restrict__ theta,
+                             const float* __restrict__ vol, int N, int HW, uint16_t* __restrict__ x) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)N * HW) return;
+    const int n = (int)(p / HW);
+    uint16_t* o = x + p * 32;
+    o[0] = f2bf(phi0[p]);
+    o[1] = f2bf((theta[n] - 90.f) / 60.f);
+    o[2] = f2bf(vol[n]);
+    for (int c = 3; c < 32; ++c) o[c] = 0;
+}
+
+inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)((n + t - 1) / t)); }
+
+int wgrad_splits(int64_t P) {
+    int64_t s = P / 4096;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    return (int)s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int tpfnn_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* stream) {
+    if (!A || !B || !D) return kEinval;
+    hipLaunchKernelGGL(mfma_selftest_k, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, D);
+    return launch_status();
+}
+
+extern "C" int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t Cin,
+                                 const uint16_t* w, const float* bias, int32_t Cout, int32_t relu,
+                                 uint16_t* y, void* stream) {
+    if (!x || !w || !y || N <= 0 || H <= 0 || W <= 0) return kEinval;
+    if (Cin % 32 || Cout % 32 || ((int64_t)H * W) % 64) return kEinval;
+    const int64_t P = (int64_t)N * H * W;
+    if (P / 64 > 0x7fffffff) return kEinval;
+    if (Cout % 64 == 0) {
+        dim3 g((unsigned)(P / 64), Cout / 64);
+        hipLaunchKernelGGL(conv3x3_fwd_k<64>, g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w, bias,
+                           Cout, relu, y);
+    } else {
+        dim3 g((unsigned)(P / 64), Cout / 32);
+        hipLaunchKernelGGL(conv3x3_fwd_k<32>, g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w, bias,
+                           Cout, relu, y);
+    }
+    return launch_status();
+}
+
+extern "C" int tpfnn_weight_flip(const uint16_t* w, int32_t Cout, int32_t Cin, uint16_t* wt, void* stream) {
+    if (!w || !wt || Cout <= 0 || Cin <= 0) return kEinval;
+    const int64_t n = (int64_t)Cout * 9 * Cin;
+    hipLaunchKernelGGL(weight_flip_k, grid1(n), dim3(256), 0, (hipStream_t)stream, w, Cout, Cin, wt);
+    return launch_status();
+}
+
+extern "C" size_t tpfnn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout) {
+    const int64_t P = (int64_t)N * H * W;
+    const int S = wgrad_splits(P);
+    const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
+    const int nb = (int)((P + chunk - 1) / chunk);
+    const size_t wpart = (size_t)nb * Cout * 9 * Cin * sizeof(float);
+    const size_t bpart = (size_t)nb * Cout * sizeof(float);
+    return wpart + bpart + 256;
+}
+
+extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_t N, int32_t H, int32_t W,
+                                   int32_t Cin, int32_t Cout, float* dw, float* db, void* work,
+                                   size_t work_bytes, void* stream) {
+    if (!x || !dy || !dw || !work || N <= 0 || H <= 0 || W <= 0) return kEinval;
+    if (Cin % 32 || Cout % 32 || ((int64_t)H * W) % 64) return kEinval;
+    if (work_bytes < tpfnn_wgrad_workspace(N, H, W, Cin, Cout)) return kEinval;
+    const int64_t P = (int64_t)N * H * W;
+    if (P > 0x7fffffff) return kEinval;
+    const int S = wgrad_splits(P);
+    const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
+    const int nb = (int)((P + chunk - 1) / chunk);
+    float* wpart = (float*)work;
+    float* bpart = wpart + (size_t)nb * Cout * 9 * Cin;
+    hipStream_t st = (hipStream_t)stream;
+    const int ncb = Cin / 32;
+    if (Cout % 64 == 0) {
+        dim3 g(Cout / 64, 9 * ncb, nb);
+        hipLaunchKernelGGL(conv3x3_wgrad_k<64>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
+                           wpart);
+    } else {
+        dim3 g(Cout / 32, 9 * ncb, nb);
+        hipLaunchKernelGGL(conv3x3_wgrad_k<32>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
+                           wpart);
+    }
+    if (hipGetLastError() != hipSuccess) return kEdevice;
+    const int64_t nw = (int64_t)Cout * 9 * Cin;
+    hipLaunchKernelGGL(sum_splits_k, grid1(nw), dim3(256), 0, st, wpart, nb, nw, dw);
+    if (hipGetLastError() != hipSuccess) return kEdevice;
+    if (db) {
+        hipLaunchKernelGGL(bias_grad_part_k, dim3(nb), dim3(256), 0, st, dy, (int)P, Cout, chunk, bpart);
+        if (hipGetLastError() != hipSuccess) return kEdevice;
+        hipLaunchKernelGGL(sum_splits_k, grid1(Cout), dim3(256), 0, st, bpart, nb, (int64_t)Cout, db);
+    }
+    return launch_status();
+}
+
+extern "C" int tpfnn_relu_bwd(const uint16_t* y, uint16_t* dy, int64_t n, void* stream) {
+    if (!y || !dy || n < 0) return kEinval;
+    if (n == 0) return kOk;
+    hipLaunchKernelGGL(relu_bwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, y, dy, n);
+    return launch_status();
+}
+
+extern "C" int tpfnn_avgpool2_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* y,
+                                  void* stream) {
+    if (!x || !y || H % 2 || W % 2 || N <= 0 || C <= 0) return kEinval;
+    const int64_t n = (int64_t)N * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(avgpool2_fwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, x, N, H, W, C, y);
+    return launch_status();
+}
+
+extern "C" int tpfnn_avgpool2_bwd(const uint16_t* dy, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* dx,
+                                  void* stream) {
+    if (!dy || !dx || H % 2 || W % 2 || N <= 0 || C <= 0) return kEinval;
+    const int64_t n = (int64_t)N * H * W * C;
+    hipLaunchKernelGGL(avgpool2_bwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, N, H, W, C, dx);
+    return launch_status();
+}
+
+extern "C" int tpfnn_upsample2_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* y,
+                                   void* stream) {
+    if (!x || !y || N <= 0 || H <= 0 || W <= 0 || C <= 0) return kEinval;
+    const int64_t n = (int64_t)N * 4 * H * W * C;
+    hipLaunchKernelGGL(upsample2_fwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, x, N, H, W, C, y);
+    return launch_status();
+}
+
+extern "C" int tpfnn_upsample2_bwd(const uint16_t* dy, int32_t N, int32_t H, int32_t W, int32_t C, uint16_t* dx,
+                                   void* stream) {
+    if (!dy || !dx || N <= 0 || H <= 0 || W <= 0 || C <= 0) return kEinval;
+    const int64_t n = (int64_t)N * H * W * C;
+    hipLaunchKernelGGL(upsample2_bwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, N, H, W, C, dx);
+    return launch_status();
+}
+
+extern "C" int tpfnn_concat(const uint16_t* a, int32_t Ca, const uint16_t* b, int32_t Cb, int64_t npix,
+                            uint16_t* y, void* stream) {
+    if (!a || !b || !y || Ca <= 0 || Cb <= 0 || npix <= 0) return kEinval;
+    const int64_t n = npix * (Ca + Cb);
+    hipLaunchKernelGGL(concat_k, grid1(n), dim3(256), 0, (hipStream_t)stream, a, Ca, b, Cb, npix, y);
+    return launch_status();
+}
+
+extern "C" int tpfnn_split(const uint16_t* dy, int32_t Ca, int32_t Cb, int64_t npix, uint16_t* da,
+                           uint16_t* db, void* stream) {
+    if (!dy || !da || !db || Ca <= 0 || Cb <= 0 || npix <= 0) return kEinval;
+    const int64_t n = npix * (Ca + Cb);
+    hipLaunchKernelGGL(split_k, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, Ca, Cb, npix, da, db);
+    return launch_status();
+}
+
+extern "C" int tpfnn_add_inplace(uint16_t* a, const uint16_t* b, int64_t n, void* stream) {
+    if (!a || !b || n < 0) return kEinval;
+    if (n == 0) return kOk;
+    hipLaunchKernelGGL(add_inplace_k, grid1(n), dim3(256), 0, (hipStream_t)stream, a, b, n);
+    return launch_status();
+}
+
+extern "C" size_t tpfnn_head_workspace(int64_t npix, int32_t C) {
+    const int64_t nblk = (npix + kHeadThreads - 1) / kHeadThreads;
+    return (size_t)nblk * (C + 2) * sizeof(double) + 256;
+}
+
+extern "C" int tpfnn_head(const uint16_t* x, int64_t npix, int32_t C, const float* w, const float* b,
+                          float* pred, const float* target, uint16_t* dx, float* dw, float* db, double* loss,
+                          void* work, size_t work_bytes, void* stream) {
+    if (!x || !w || !b || !pred || npix <= 0 || C <= 0 || C > 32) return kEinval;
+    if (target && (!dx || !dw || !db || !loss || !work || work_bytes < tpfnn_head_workspace(npix, C)))
+        return kEinval;
+    const int64_t nblk = (npix + kHeadThreads - 1) / kHeadThreads;
+    if (nblk > 0x7fffffff) return kEinval;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(head_k, dim3((unsigned)nblk), dim3(kHeadThreads), 0, st, x, npix, C, w, b, pred, target,
+                       dx, (double*)work);
+    if (hipGetLastError() != hipSuccess) return kEdevice;
+    if (target)
+        hipLaunchKernelGGL(head_final_k, dim3(1), dim3(64), 0, st, (const double*)work, (int)nblk, C, npix, dw,
+                           db, loss);
+    return launch_status();
+}
+
+extern "C" int tpfnn_adam(float* p, float* m, float* v, const float* g, uint16_t* p_bf16, int64_t n, float lr,
+                          float beta1, float beta2, float eps, int32_t t, void* stream) {
+    if (!p || !m || !v || !g || n <= 0 || t <= 0) return kEinval;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(adam_k, grid1(n), dim3(256), 0, (hipStream_t)stream, p, m, v, g, p_bf16, n, lr, beta1,
+                       beta2, eps, c1, c2);
+    return launch_status();
+}
+
+extern "C" int tpfnn_to_bf16(const float* x, uint16_t* y, int64_t n, void* stream) {
+    if (!x || !y || n < 0) return kEinval;
+    if (n == 0) return kOk;
+    hipLaunchKernelGGL(to_bf16_k, grid1(n), dim3(256), 0, (hipStream_t)stream, x, y, n);
+    return launch_status();
+}
+
+extern "C" int tpfnn_from_bf16(const uint16_t* x, float* y, int64_t n, void* stream) {
+    if (!x || !y || n < 0) return kEinval;
+    if (n == 0) return kOk;
+    hipLaunchKernelGGL(from_bf16_k, grid1(n), dim3(256), 0, (hipStream_t)stream, x, y, n);
+    return launch_status();
+}
+
+extern "C" int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* dst, int32_t dh,
+                              int32_t dw, void* stream) {
+    if (!src || !dst || N <= 0 || sh <= 0 || sw <= 0 || dh <= 0 || dw <= 0) return kEinval;
+    const int64_t n = (int64_t)N * dh * dw;
+    hipLaunchKernelGGL(resample_k, grid1(n), dim3(256), 0, (hipStream_t)stream, src, N, sh, sw, dst, dh, dw);
+    return launch_status();
+}
+
+extern "C" int tpfnn_pack_input(const float* phi0, const float* theta_deg, const float* vol, int32_t N,
+                                int32_t H, int32_t W, uint16_t* x, void* stream) {
+    if (!phi0 || !theta_deg || !vol || !x || N <= 0 || H <= 0 || W <= 0) return kEinval;
+    const int64_t n = (int64_t)N * H * W;
+    hipLaunchKernelGGL(pack_input_k, grid1(n), dim3(256), 0, (hipStream_t)stream, phi0, theta_deg, vol, N,
+                       H * W, x);
+    return launch_status();
+}

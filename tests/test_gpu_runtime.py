@@ -176,7 +176,9 @@ def test_edge_cases_fp64(orc, name, factory):
     ctx.step(60)
     sim = oracle_run(orc, sp, 60)
     for a, b in zip(ctx.moments(0), sim.moments()):
-        assert np.abs(a - b).max() <= 1e-11 * max(np.abs(b).max(), 1e-30)
+        # relative to the field maximum, with an absolute floor for fields that
+        # are rounding noise (the 3x3 cases have |u| ~ 1e-12)
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max() + 1e-15
     ctx.close()
 
 
