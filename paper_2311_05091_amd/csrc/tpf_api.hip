@@ -24,11 +24,15 @@ struct TileShape {
 };
 // codes are stable across builds.  1-7: tile kernel (256 threads, whole-tile
 // LDS window); 8-11: strip kernel (one wavefront marching down a 64-column
-// strip of ty rows).
+// strip of ty rows); 12-14: pipelined strip kernel (one wavefront per
+// 60-column strip, next row's loads in flight during the current row);
+// 15-16: strip kernel compiled for five wavefronts per SIMD.
 static const TileShape kTiles[] = {{1, 64, 4, 256},  {2, 64, 8, 256},   {3, 64, 16, 256},
                                    {4, 128, 8, 256}, {5, 32, 8, 256},   {6, 64, 32, 256},
                                    {7, 128, 16, 256}, {8, 64, 16, 64},  {9, 64, 32, 64},
-                                   {10, 64, 64, 64}, {11, 64, 128, 64}};
+                                   {10, 64, 64, 64}, {11, 64, 128, 64}, {12, 60, 16, 64},
+                                   {13, 60, 32, 64}, {14, 60, 64, 64}, {15, 64, 32, 64},
+                                   {16, 64, 16, 64}};
 static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 static const int kDefaultTile = 9;
 
@@ -161,65 +165,74 @@ static int validate(const tpf_domain_params& p) {
     return TPF_OK;
 }
 
+template <typename T>
+static void fill_kconst(const tpf_domain_params& p, const HostDomain& h, KConst<T>& K) {
+    const double c2 = p.d0;
+    const double w0 = (1.0 - c2) * (1.0 - c2);
+    K.c2 = (T)c2;
+    K.w0 = (T)w0;
+    K.gam0 = (T)h.gamma[0];
+    K.gam1 = (T)h.gamma[1];
+    K.gam2 = (T)h.gamma[2];
+    K.gT3 = (T)(h.gammaT / 3.0);
+    K.inv_gam0 = (T)(1.0 / h.gamma[0]);
+    K.inv_gam2 = (T)(1.0 / h.gamma[2]);
+    K.c12D = (T)(12.0 / p.D);
+    K.c3D4 = (T)(0.75 * p.D);
+    K.eta = (T)h.eta;
+    K.Mcst = (T)p.M_cst;
+    K.Mdeg = (T)p.M_deg;
+    K.Mdeg_frac = (T)(p.M_deg / (p.M_cst + p.M_deg));
+    K.s0 = (T)p.s_phi[0];
+    K.s1 = (T)(1.0 / p.tau_phi);
+    K.s2 = (T)p.s_phi[1];
+    K.s3 = (T)p.s_phi[2];
+    K.s4 = (T)p.s_phi[3];
+    K.rho0 = (T)p.rho[0];
+    K.rho1 = (T)p.rho[1];
+    K.rho2 = (T)p.rho[2];
+    K.muv0 = (T)p.mu[0];
+    K.muv1 = (T)p.mu[1];
+    K.muv2 = (T)p.mu[2];
+    K.drho0 = (T)(p.rho[0] - p.rho[2]);
+    K.drho1 = (T)(p.rho[1] - p.rho[2]);
+    K.Sfac = (T)((p.rho[1] - p.rho[2]) / h.gamma[1]);
+    K.sg0 = (T)p.s_g[0];
+    K.sg1 = (T)p.s_g[1];
+    K.sg3 = (T)p.s_g[2];
+    K.sg4 = (T)p.s_g[3];
+    // mu/(rho (1 - phi0)) = (1/s2a - 1/2)(c^2 - c_s^2)/2 = (1/s2b - 1/2) c_s^2  (Sec. 3)
+    K.inv_cfa = (T)(2.0 / (1.0 - c2));
+    K.inv_cfb = (T)(1.0 / c2);
+    K.Fbx = (T)p.Fb[0];
+    K.Fby = (T)p.Fb[1];
+    K.uwx = (T)p.u_wall[0];
+    K.uwy = (T)p.u_wall[1];
+    K.gauge = (T)p.rho_gauge;
+    // p = c_s^2/(1 - w0) [ sum_{i != 0} g_i + (1/2 + H) u.grad(rho)
+    //      - w0 (rho u - S).u/(c^2 - c_s^2) + (K/c^2)(dt/2) d_t((rho u - S).u) ]
+    // 2D: K = 1 - d0, H = K [ (1 - d0)/s0 - (2 - 4 d0)/s2a + (1 - 3 d0)/2 ]
+    K.pfac = (T)(c2 / (1.0 - w0));
+    K.pw = (T)(w0 / (1.0 - c2));
+    K.Kp = (T)(1.0 - c2);
+    K.AH = (T)((1.0 - c2) / p.s_g[0] + 0.5 * (1.0 - 3.0 * c2));
+    K.BH = (T)(2.0 - 4.0 * c2);
+}
+
 static void fill_constants(HostDomain& h) {
     const tpf_domain_params& p = h.p;
     DomDev& d = h.dev;
     derive_gamma(p, h.k, h.gamma, h.gammaT);
-    const double c2 = p.d0;
+    // (M_cst + M_deg)/gamma_1 = (1/s1 - 1/2) eta c_s^2  (Sec. 3)
+    h.eta = (p.M_cst + p.M_deg) / (h.gamma[1] * (p.tau_phi - 0.5) * p.d0);
     d.nx = p.nx;
     d.ny = p.ny;
     d.px = p.periodic_x ? 1 : 0;
     d.py = p.periodic_y ? 1 : 0;
     d.has_s = (p.rho[1] != p.rho[2]) ? 1 : 0;
-    d.c2 = c2;
-    d.w0 = (1.0 - c2) * (1.0 - c2);
-    d.gam0 = h.gamma[0];
-    d.gam1 = h.gamma[1];
-    d.gam2 = h.gamma[2];
-    d.gT3 = h.gammaT / 3.0;
-    d.inv_gam0 = 1.0 / h.gamma[0];
-    d.inv_gam2 = 1.0 / h.gamma[2];
-    d.c12D = 12.0 / p.D;
-    d.c3D4 = 0.75 * p.D;
-    // (M_cst + M_deg)/gamma_1 = (1/s1 - 1/2) eta c_s^2  (Sec. 3)
-    h.eta = (p.M_cst + p.M_deg) / (h.gamma[1] * (p.tau_phi - 0.5) * c2);
-    d.eta = h.eta;
-    d.Mcst = p.M_cst;
-    d.Mdeg = p.M_deg;
-    d.Mdeg_frac = p.M_deg / (p.M_cst + p.M_deg);
-    d.sphi[0] = p.s_phi[0];
-    d.sphi[1] = 1.0 / p.tau_phi;
-    d.sphi[2] = p.s_phi[1];
-    d.sphi[3] = p.s_phi[2];
-    d.sphi[4] = p.s_phi[3];
-    d.rho0 = p.rho[0];
-    d.rho1 = p.rho[1];
-    d.rho2 = p.rho[2];
-    d.muv0 = p.mu[0];
-    d.muv1 = p.mu[1];
-    d.muv2 = p.mu[2];
-    d.drho0 = p.rho[0] - p.rho[2];
-    d.drho1 = p.rho[1] - p.rho[2];
-    d.Sfac = (p.rho[1] - p.rho[2]) / h.gamma[1];
-    d.sg0 = p.s_g[0];
-    d.sg1 = p.s_g[1];
-    d.sg3 = p.s_g[2];
-    d.sg4 = p.s_g[3];
-    d.cfa = 0.5 * (1.0 - c2);
-    d.cfb = c2;
-    d.Fbx = p.Fb[0];
-    d.Fby = p.Fb[1];
-    d.uwx = p.u_wall[0];
-    d.uwy = p.u_wall[1];
-    d.gauge = p.rho_gauge;
-    // p = c_s^2/(1 - w0) [ sum_{i != 0} g_i + (1/2 + H) u.grad(rho)
-    //      - w0 (rho u - S).u/(c^2 - c_s^2) + (K/c^2)(dt/2) d_t((rho u - S).u) ]
-    // 2D: K = 1 - d0, H = K [ (1 - d0)/s0 - (2 - 4 d0)/s2a + (1 - 3 d0)/2 ]
-    d.pfac = c2 / (1.0 - d.w0);
-    d.pw = d.w0 / (1.0 - c2);
-    d.Kp = 1.0 - c2;
-    d.AH = (1.0 - c2) / p.s_g[0] + 0.5 * (1.0 - 3.0 * c2);
-    d.BH = 2.0 - 4.0 * c2;
+    d.bh_zero = (2.0 - 4.0 * p.d0 == 0.0) ? 1 : 0;
+    fill_kconst<double>(p, h, d.kd);
+    fill_kconst<float>(p, h, d.kf);
 }
 
 // ---------------------------------------------------------------------------
@@ -288,9 +301,28 @@ static hipError_t launch_strip_t(tpf_ctx* c, int t0, int ntiles, int offset, dou
     return hipGetLastError();
 }
 
+template <typename T, int CH, bool S, int MODE>
+static hipError_t launch_strip_o5_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
+    hipLaunchKernelGGL((strip_kernel_o5<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
+                       c->d_tiles + t0, ntiles, offset, mom);
+    return hipGetLastError();
+}
+
+template <typename T, int CH, bool S, int MODE>
+static hipError_t launch_strip2_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
+    hipLaunchKernelGGL((strip2_kernel<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
+                       c->d_tiles + t0, ntiles, offset, mom);
+    return hipGetLastError();
+}
+
 template <typename T, bool S, int MODE>
 static hipError_t launch_step_shape(tpf_ctx* c, int code, int t0, int n, int offset, double* mom) {
     switch (code) {
+        case 15: return launch_strip_o5_t<T, 32, S, MODE>(c, t0, n, offset, mom);
+        case 16: return launch_strip_o5_t<T, 16, S, MODE>(c, t0, n, offset, mom);
+        case 12: return launch_strip2_t<T, 16, S, MODE>(c, t0, n, offset, mom);
+        case 13: return launch_strip2_t<T, 32, S, MODE>(c, t0, n, offset, mom);
+        case 14: return launch_strip2_t<T, 64, S, MODE>(c, t0, n, offset, mom);
         case 8: return launch_strip_t<T, 16, S, MODE>(c, t0, n, offset, mom);
         case 9: return launch_strip_t<T, 32, S, MODE>(c, t0, n, offset, mom);
         case 10: return launch_strip_t<T, 64, S, MODE>(c, t0, n, offset, mom);

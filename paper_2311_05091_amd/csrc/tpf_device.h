@@ -7,20 +7,57 @@
 
 namespace tpf {
 
+// Pointers into the arena are stored generically in the descriptor; casting
+// them to the global address space lets the compiler emit global (not flat)
+// memory instructions, whose completion is tracked apart from LDS traffic.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(void* p) {
+    return (gptr<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ gptr<const T> gpc(const void* p) {
+    return (gptr<const T>)p;
+}
+
 // D2Q9 velocities in the order of the rows of M0 (App. A):
 // 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1) 7 (-1,-1) 8 (1,-1)
 __device__ __constant__ const int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ __constant__ const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ __constant__ const int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
+// Per-domain constants of the step in one precision (derived on the host in
+// FP64, stored once as double and once as float so that kernels read them
+// in their own precision without conversions).
+template <typename T>
+struct KConst {
+    T c2, w0;                    // c_s^2 = d0, omega_0
+    T gam0, gam1, gam2, gT3;     // gamma_p, gamma^T/3 (Sec. 2.1)
+    T inv_gam0, inv_gam2;
+    T c12D, c3D4;                // 12/D, 3D/4
+    T eta, Mcst, Mdeg, Mdeg_frac;  // Mdeg_frac = M_deg/(M_cst + M_deg)
+    T s0, s1, s2, s3, s4;        // CH rates
+    T rho0, rho1, rho2, muv0, muv1, muv2;
+    T drho0, drho1;              // rho0 - rho2, rho1 - rho2
+    T Sfac;                      // (rho1 - rho2)/gamma1
+    T sg0, sg1, sg3, sg4;        // NS rates (s2a, s2b per node)
+    T inv_cfa, inv_cfb;          // 2/(1 - c_s^2) and 1/c_s^2
+    T Fbx, Fby, uwx, uwy, gauge;
+    T pfac, pw, Kp, AH, BH;      // p = pfac [ sum_{i>0} g_i + (1/2 + H) Q - pw B + Kp/2 dB ],
+                                 // H = Kp (AH - BH/s2a)
+};
+
 // Per-domain descriptor in device memory.  Pointers are element pointers of
-// the storage precision; constants are derived on the host in FP64.
+// the storage precision.
 struct DomDev {
     int32_t nx, ny, px, py;      // size and periodicity (1) / walls (0)
     int32_t parity;              // buffer holding the current post-collision state
     int32_t live;                // 1 while the domain is being advanced
     int32_t has_s;               // rho1 != rho2: extra flux S, F_c and C are active
-    int32_t pad0;
+    int32_t bh_zero;             // BH == 0 (d0 = 1/2): H does not depend on s2a
     void* f[2];                  // [9][ny][nx] CH populations (ping-pong)
     void* g[2];                  // [9][ny][nx] NS populations (ping-pong)
     void* phi0;                  // [ny][nx] solid field
@@ -29,25 +66,16 @@ struct DomDev {
     void* lagC;                  // [3][ny][nx] sym(S u) of the previous step (has_s)
     void* psi[2];                // [ny][nx]    S_x u_y - S_y u_x (has_s, ping-pong)
     double* snap;                // [ny][nx]    phi1 at the last residual check
-    // lattice
-    double c2, w0;               // c_s^2 = d0, omega_0
-    // chemical potentials (Sec. 2.1)
-    double gam0, gam1, gam2, gT3;  // gamma_p, gamma^T/3
-    double inv_gam0, inv_gam2;
-    double c12D, c3D4;           // 12/D, 3D/4
-    // CH lattice (Sec. 3)
-    double eta, Mcst, Mdeg, Mdeg_frac;  // Mdeg_frac = M_deg/(M_cst + M_deg)
-    double sphi[5];              // s0, s1, s2, s3, s4
-    // NS lattice (Sec. 2.3, 3)
-    double rho0, rho1, rho2, muv0, muv1, muv2;
-    double drho0, drho1;         // rho0 - rho2, rho1 - rho2
-    double Sfac;                 // (rho1 - rho2)/gamma1
-    double sg0, sg1, sg3, sg4;
-    double cfa, cfb;             // (1 - c_s^2)/2 and c_s^2
-    double Fbx, Fby, uwx, uwy, gauge;
-    double pfac, pw, Kp, AH, BH; // p = pfac [ sum_{i>0} g_i + (1/2 + H) Q - pw B + Kp/2 dB ],
-                                 // H = Kp (AH - BH/s2a)
+    KConst<double> kd;
+    KConst<float> kf;
 };
+
+template <typename T>
+__device__ __forceinline__ const KConst<T>& kconst(const DomDev& d);
+template <>
+__device__ __forceinline__ const KConst<double>& kconst<double>(const DomDev& d) { return d.kd; }
+template <>
+__device__ __forceinline__ const KConst<float>& kconst<float>(const DomDev& d) { return d.kf; }
 
 // Window cell -> node index.  Periodic axes wrap; across a half-way wall the
 // node is the even mirror (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).  Cells
@@ -70,7 +98,7 @@ __device__ __forceinline__ int map_index(int j, int n, int periodic) {
 // post-collision population of the node itself across a wall (half-way
 // bounce-back, Sec. 4).
 template <typename T>
-__device__ __forceinline__ T pull(const T* __restrict__ fin, int q, int x, int y, int nx, int ny,
+__device__ __forceinline__ T pull(gptr<const T> fin, int q, int x, int y, int nx, int ny,
                                   int px, int py, int N) {
     int xs = x - kCx[q], ys = y - kCy[q];
     bool out = false;
@@ -87,24 +115,24 @@ template <typename T>
 __device__ __forceinline__ void stencil9(const T* s, int i, int W, T& gx, T& gy, T& lap) {
     T C = s[i], E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
     T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
-    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) / T(12);
-    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) / T(12);
-    lap = (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) / T(6);
+    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) * T(1.0 / 12.0);
+    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) * T(1.0 / 12.0);
+    lap = (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) * T(1.0 / 6.0);
 }
 
 template <typename T>
 __device__ __forceinline__ void grad9(const T* s, int i, int W, T& gx, T& gy) {
     T E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
     T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
-    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) / T(12);
-    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) / T(12);
+    gx = (T(4) * (E - Wv) + (NE - NW + SE - SW)) * T(1.0 / 12.0);
+    gy = (T(4) * (Nn - Ss) + (NE - SE + NW - SW)) * T(1.0 / 12.0);
 }
 
 template <typename T>
 __device__ __forceinline__ T lap9(const T* s, int i, int W) {
     T C = s[i], E = s[i + 1], Wv = s[i - 1], Nn = s[i + W], Ss = s[i - W];
     T NE = s[i + W + 1], NW = s[i + W - 1], SE = s[i - W + 1], SW = s[i - W - 1];
-    return (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) / T(6);
+    return (T(4) * (E + Wv + Nn + Ss) + (NE + NW + SE + SW) - T(20) * C) * T(1.0 / 6.0);
 }
 
 // mu_p = gamma_p [ (12/D) phi (1-phi)(1-2phi) - (3D/4) lap(phi) ]   (Sec. 2.1)
@@ -115,14 +143,13 @@ __device__ __forceinline__ T chem(T gam, T c12D, T c3D4, T phi, T lap) {
 
 // mubar_1 = (gamma^T/3) [ (mu1 - mu0)/gamma0 + (mu1 - mu2)/gamma2 ]  (Eq. eq-CHmodel)
 template <typename T>
-__device__ __forceinline__ T mubar1(const DomDev& d, T phi0, T phi1, T lap0, T lap1, T& mu0,
+__device__ __forceinline__ T mubar1(const KConst<T>& K, T phi0, T phi1, T lap0, T lap1, T& mu0,
                                     T& mu1, T& mu2) {
-    const T c12D = T(d.c12D), c3D4 = T(d.c3D4);
     T phi2 = T(1) - phi0 - phi1;
-    mu0 = chem(T(d.gam0), c12D, c3D4, phi0, lap0);
-    mu1 = chem(T(d.gam1), c12D, c3D4, phi1, lap1);
-    mu2 = chem(T(d.gam2), c12D, c3D4, phi2, -lap0 - lap1);
-    return T(d.gT3) * ((mu1 - mu0) * T(d.inv_gam0) + (mu1 - mu2) * T(d.inv_gam2));
+    mu0 = chem(K.gam0, K.c12D, K.c3D4, phi0, lap0);
+    mu1 = chem(K.gam1, K.c12D, K.c3D4, phi1, lap1);
+    mu2 = chem(K.gam2, K.c12D, K.c3D4, phi2, -lap0 - lap1);
+    return K.gT3 * ((mu1 - mu0) * K.inv_gam0 + (mu1 - mu2) * K.inv_gam2);
 }
 
 // Natural moments m = M0 p (rows 1, cx, cy, cx^2, cy^2, cxcy, cxcy^2, cx^2cy, cx^2cy^2).

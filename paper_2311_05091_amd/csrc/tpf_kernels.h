@@ -33,25 +33,25 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // the lagged fields of the node, forms the forces, u, p and writes either the
 // post-collision populations and lagged fields or the moments.
 template <typename T, int MODE>
-__device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, int N, T ph0, T ph1,
+__device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K, bool dS, int id, int N, T ph0, T ph1,
                                             T gx0, T gy0, T lap0, T gx1, T gy1, T lap1, T mub,
-                                            T gmx, T gmy, T dpsix, T dpsiy, T (&fp)[9], T (&gp)[9],
+                                            T gmx, T gmy, T dpsix, T dpsiy, T (&fp)[9], T (&gq)[9],
                                             T lAx, T lAy, T lB, T lCxx, T lCyy, T lCxy, int cur,
                                             double* __restrict__ mom_out) {
-    const T c2 = T(d.c2);
+    const T c2 = K.c2;
     T mu0, mu1, mu2;
-    (void)mubar1<T>(d, ph0, ph1, lap0, lap1, mu0, mu1, mu2);
+    (void)mubar1<T>(K, ph0, ph1, lap0, lap1, mu0, mu1, mu2);
 
     // degenerate mobility, 2f1s form f = phi1 (1 - phi1)(1 - phi0) (Sec. 4)
     const T fdeg = ph1 * (T(1) - ph1) * (T(1) - ph0);
-    const T a = T(d.Mdeg_frac) * (T(1) - fdeg);
+    const T a = K.Mdeg_frac * (T(1) - fdeg);
 
     // density, viscosity (linear in phi_p), grad(rho)
     const T ph2 = T(1) - ph0 - ph1;
-    const T rho = T(d.rho0) * ph0 + T(d.rho1) * ph1 + T(d.rho2) * ph2;
-    const T muv = T(d.muv0) * ph0 + T(d.muv1) * ph1 + T(d.muv2) * ph2;
-    const T drx = T(d.drho0) * gx0 + T(d.drho1) * gx1;
-    const T dry = T(d.drho0) * gy0 + T(d.drho1) * gy1;
+    const T rho = K.rho0 * ph0 + K.rho1 * ph1 + K.rho2 * ph2;
+    const T muv = K.muv0 * ph0 + K.muv1 * ph1 + K.muv2 * ph2;
+    const T drx = K.drho0 * gx0 + K.drho1 * gx1;
+    const T dry = K.drho0 * gy0 + K.drho1 * gy1;
 
     // surface tension F_s = sum_p mu_p grad(phi_p)
     T Fx = mu0 * gx0 + mu1 * gx1 + mu2 * (-gx0 - gx1);
@@ -59,36 +59,36 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
     T Sx = T(0), Sy = T(0);
     if (dS) {
         // S = (rho1 - rho2) M grad(mubar1)/gamma1; F_c from the previous psi
-        const T Mob = T(d.Mcst) + T(d.Mdeg) * fdeg;
-        Sx = T(d.Sfac) * Mob * gmx;
-        Sy = T(d.Sfac) * Mob * gmy;
+        const T Mob = K.Mcst + K.Mdeg * fdeg;
+        Sx = K.Sfac * Mob * gmx;
+        Sy = K.Sfac * Mob * gmy;
         Fx += T(-0.5) * dpsiy;
         Fy += T(0.5) * dpsix;
     }
-    Fx += T(d.Fbx);
-    Fy += T(d.Fby);
+    Fx += K.Fbx;
+    Fy += K.Fby;
 
     // NS moments; velocity with the solid correction (Sec. 3)
     T mg[9];
-    nat_moments(gp, mg);
+    nat_moments(gq, mg);
     const T inv_rho = T(1) / rho;
     const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
     const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
-    const T fsx = T(d.uwx) - usx, fsy = T(d.uwy) - usy;
+    const T fsx = K.uwx - usx, fsy = K.uwy - usy;
     const T ux = usx + T(0.5) * ph0 * fsx;
     const T uy = usy + T(0.5) * ph0 * fsy;
 
     // per-node NS rates from mu/(rho (1 - phi0)) (Sec. 3)
     const T om = T(1) - ph0;
-    const T s2a = om / (muv * inv_rho / T(d.cfa) + T(0.5) * om);
-    const T s2b = om / (muv * inv_rho / T(d.cfb) + T(0.5) * om);
+    const T s2a = om / (muv * inv_rho * K.inv_cfa + T(0.5) * om);
+    const T s2b = om / (muv * inv_rho * K.inv_cfb + T(0.5) * om);
 
     // pressure (Sec. 3, 2D constants)
     const T Q = ux * drx + uy * dry;
     const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
-    const T H = T(d.Kp) * (T(d.AH) - (d.BH == 0.0 ? T(0) : T(d.BH) / s2a));
-    const T p = T(d.pfac) * ((mg[0] - gp[0]) + (T(0.5) + H) * Q - T(d.pw) * Bn +
-                             T(0.5) * T(d.Kp) * (Bn - lB));
+    const T H = K.Kp * (K.AH - (d.bh_zero ? T(0) : K.BH / s2a));
+    const T p = K.pfac * ((mg[0] - gq[0]) + (T(0.5) + H) * Q - K.pw * Bn +
+                             T(0.5) * K.Kp * (Bn - lB));
 
     if constexpr (MODE == kModeMoments) {
         mom_out[id] = double(ph1);
@@ -97,8 +97,8 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
         mom_out[3 * N + id] = double(p);
         return;
     }
-    T* __restrict__ fout = (T*)d.f[cur ^ 1];
-    T* __restrict__ gout = (T*)d.g[cur ^ 1];
+    gptr<T> fout = gp<T>(d.f[cur ^ 1]);
+    gptr<T> gout = gp<T>(d.g[cur ^ 1]);
 
     // ---- CH collision in Hermite space ----
     {
@@ -106,12 +106,11 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
         nat_moments(fp, m);
         to_hermite(m, h, c2);
         const T Ax = ph1 * ux, Ay = ph1 * uy;
-        const T emu = T(d.eta) * mub;
+        const T emu = K.eta * mub;
         // d_t(phi u) by explicit Euler, plus the degenerate-mobility correction
-        const T Wx = (Ax - lAx) + a * T(d.eta) * c2 * gmx;
-        const T Wy = (Ay - lAy) + a * T(d.eta) * c2 * gmy;
-        const T s0 = T(d.sphi[0]), s1 = T(d.sphi[1]), s2 = T(d.sphi[2]);
-        const T s3 = T(d.sphi[3]), s4 = T(d.sphi[4]);
+        const T Wx = (Ax - lAx) + a * K.eta * c2 * gmx;
+        const T Wy = (Ay - lAy) + a * K.eta * c2 * gmy;
+        const T s0 = K.s0, s1 = K.s1, s2 = K.s2, s3 = K.s3, s4 = K.s4;
         const T e3 = c2 * (emu - ph1);
         h[0] = h[0] - s0 * (h[0] - ph1);
         h[1] = h[1] - s1 * (h[1] - Ax) + (T(1) - T(0.5) * s1) * Wx;
@@ -126,7 +125,7 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
         from_hermite(h, fo, c2);
 #pragma unroll
         for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(fo[q], &fout[q * N + id]);
-        T* lagA = (T*)d.lagA;
+        gptr<T> lagA = gp<T>(d.lagA);
         lagA[id] = Ax;
         lagA[N + id] = Ay;
     }
@@ -155,8 +154,8 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
         const T Mxy = ux * Fy + Fx * uy - dCxy + c2 * (ux * dry + drx * uy);
         T h[9];
         to_hermite(mg, h, c2);
-        const T gauge = T(d.gauge);
-        const T sg0 = T(d.sg0), sg1 = T(d.sg1), sg3 = T(d.sg3), sg4 = T(d.sg4);
+        const T gauge = K.gauge;
+        const T sg0 = K.sg0, sg1 = K.sg1, sg3 = K.sg3, sg4 = K.sg4;
         h[0] = h[0] - sg0 * (h[0] - gauge) + (T(1) - T(0.5) * sg0) * Q;
         h[1] = h[1] - sg1 * (h[1] - Jx) + (T(1) - T(0.5) * sg1) * Gx;
         h[2] = h[2] - sg1 * (h[2] - Jy) + (T(1) - T(0.5) * sg1) * Gy;
@@ -170,20 +169,20 @@ __device__ __forceinline__ void node_update(const DomDev& d, bool dS, int id, in
         from_hermite(h, go, c2);
 #pragma unroll
         for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(go[q], &gout[q * N + id]);
-        ((T*)d.lagB)[id] = Bn;
+        gp<T>(d.lagB)[id] = Bn;
         if (dS) {
-            T* lagC = (T*)d.lagC;
+            gptr<T> lagC = gp<T>(d.lagC);
             lagC[id] = Cxx;
             lagC[N + id] = Cyy;
             lagC[2 * N + id] = Cxy;
-            ((T*)d.psi[cur ^ 1])[id] = Sx * uy - Sy * ux;
+            gp<T>(d.psi[cur ^ 1])[id] = Sx * uy - Sy * ux;
         }
     }
 }
 
 // Pulled populations of both lattices at node (x, y).
 template <typename T>
-__device__ __forceinline__ void pull9(const T* __restrict__ fin, int x, int y, int nx, int ny, int px,
+__device__ __forceinline__ void pull9(gptr<const T> fin, int x, int y, int nx, int ny, int px,
                                       int py, int N, T (&out)[9]) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = pull(fin, q, x, y, nx, ny, px, py, N);
@@ -205,13 +204,14 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
     const int4 tile = tiles[t];
     const DomDev& d = doms[tile.x];
     if (!d.live && MODE == kModeStep) return;
+    const KConst<T> K = kconst<T>(d);
     const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
     const int N = nx * ny;
     const int x0 = tile.y, y0 = tile.z;
     const int cur = (d.parity + step_offset) & 1;
-    const T* __restrict__ fin = (const T*)d.f[cur];
-    const T* __restrict__ gin = (const T*)d.g[cur];
-    const T* __restrict__ phi0 = (const T*)d.phi0;
+    gptr<const T> fin = gpc<T>(d.f[cur]);
+    gptr<const T> gin = gpc<T>(d.g[cur]);
+    gptr<const T> phi0 = gpc<T>(d.phi0);
     const int tid = threadIdx.x;
 
     // ---- 1. phi0 and phi1 = sum_q f_q on the halo-2 window ----
@@ -231,12 +231,12 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
     // HAS_S instances serve batches in which some domain has the flux S; the
     // per-domain flag selects the branch (uniform across the workgroup)
     const bool dS = HAS_S && d.has_s;
-    const T* __restrict__ psi_in = dS ? (const T*)d.psi[cur] : nullptr;
+    gptr<const T> psi_in = dS ? gpc<T>(d.psi[cur]) : nullptr;
     for (int k = tid; k < VX * VY; k += NT) {
         const int vx = k % VX, vy = k / VX;
         const int i = (vy + 1) * WX + (vx + 1);
         T mu0, mu1, mu2;
-        s_mub[k] = mubar1<T>(d, s_phi0[i], s_phi1[i], lap9(s_phi0, i, WX), lap9(s_phi1, i, WX),
+        s_mub[k] = mubar1<T>(K, s_phi0[i], s_phi1[i], lap9(s_phi0, i, WX), lap9(s_phi1, i, WX),
                              mu0, mu1, mu2);
         if (dS) {
             const int sx = map_index(x0 - 1 + vx, nx, px);
@@ -247,9 +247,9 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
     __syncthreads();
 
     // ---- 3. per-node macroscopic fields and collisions ----
-    const T* __restrict__ lagA = (const T*)d.lagA;
-    const T* __restrict__ lagB = (const T*)d.lagB;
-    const T* __restrict__ lagC = (const T*)d.lagC;
+    gptr<const T> lagA = gpc<T>(d.lagA);
+    gptr<const T> lagB = gpc<T>(d.lagB);
+    gptr<const T> lagC = gpc<T>(d.lagC);
     for (int k = tid; k < TX * TY; k += NT) {
         const int lx = k % TX, ly = k / TX;
         const int x = x0 + lx, y = y0 + ly;
@@ -268,11 +268,11 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
             lCyy = lagC[N + id];
             lCxy = lagC[2 * N + id];
         }
-        T fp[9], gp[9];
-        pull9(gin, x, y, nx, ny, px, py, N, gp);
+        T fp[9], gq[9];
+        pull9(gin, x, y, nx, ny, px, py, N, gq);
         pull9(fin, x, y, nx, ny, px, py, N, fp);
-        node_update<T, MODE>(d, dS, id, N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
-                             s_mub[iv], gmx, gmy, dpx, dpy, fp, gp, lagA[id], lagA[N + id], lagB[id],
+        node_update<T, MODE>(d, K, dS, id, N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
+                             s_mub[iv], gmx, gmy, dpx, dpy, fp, gq, lagA[id], lagA[N + id], lagB[id],
                              lCxx, lCyy, lCxy, cur, mom_out);
     }
 }
@@ -297,32 +297,32 @@ struct StripShared {
 };
 
 template <typename T, int CH, bool HAS_S, int MODE>
-__device__ __forceinline__ void strip_iter(const DomDev& d, StripShared<T, HAS_S>& sh, int r, int x0,
+__device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, StripShared<T, HAS_S>& sh, int r, int x0,
                                            int y0, int lane, int cur, bool dS, T (&fL)[9], T (&fU)[9],
                                            double* __restrict__ mom_out) {
     const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
     const int N = nx * ny;
-    const T* __restrict__ fin = (const T*)d.f[cur];
-    const T* __restrict__ phi0 = (const T*)d.phi0;
+    gptr<const T> fin = gpc<T>(d.f[cur]);
+    gptr<const T> phi0 = gpc<T>(d.phi0);
     const int yr = y0 - 2 + r;          // phi row loaded in this iteration
     const int yu = yr - 2;              // row updated in this iteration
     const int x = x0 + lane;
     const bool do_update = (r >= 4) && (yu < ny) && (x < nx);
 
     // prefetch the NS populations and lagged fields of the row to update
-    T gp[9];
+    T gpl[9];
     T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
     int idu = 0;
     if (do_update) {
         idu = yu * nx + x;
-        pull9((const T*)d.g[cur], x, yu, nx, ny, px, py, N, gp);
-        lAx = ((const T*)d.lagA)[idu];
-        lAy = ((const T*)d.lagA)[N + idu];
-        lB = ((const T*)d.lagB)[idu];
+        pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gpl);
+        lAx = gpc<T>(d.lagA)[idu];
+        lAy = gpc<T>(d.lagA)[N + idu];
+        lB = gpc<T>(d.lagB)[idu];
         if (dS) {
-            lCxx = ((const T*)d.lagC)[idu];
-            lCyy = ((const T*)d.lagC)[N + idu];
-            lCxy = ((const T*)d.lagC)[2 * N + idu];
+            lCxx = gpc<T>(d.lagC)[idu];
+            lCyy = gpc<T>(d.lagC)[N + idu];
+            lCxy = gpc<T>(d.lagC)[2 * N + idu];
         }
     }
 
@@ -361,16 +361,16 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, StripShared<T, HAS_S
         for (int c = lane; c < 66; c += 64) {
             const int i = c + 1;
             const T l1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
-                          (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) / T(6);
+                          (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
             const T l0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
-                          (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) / T(6);
+                          (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
             T mu0, mu1, mu2;
-            sh.mub[slot3][c] = mubar1<T>(d, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
+            sh.mub[slot3][c] = mubar1<T>(K, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
             if constexpr (HAS_S) {
                 if (dS) {
                     const int sx = map_index(x0 - 1 + c, nx, px);
                     const int sy = map_index(yr - 1, ny, py);
-                    sh.psi[slot3][c] = ((const T*)d.psi[cur])[sy * nx + sx];
+                    sh.psi[slot3][c] = gpc<T>(d.psi[cur])[sy * nx + sx];
                 }
             }
         }
@@ -390,41 +390,41 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, StripShared<T, HAS_S
         const T* mm = sh.mub[(r + 1) % 3];   // row yu - 1
         const T* m0 = sh.mub[(r + 2) % 3];   // row yu
         const T* mp = sh.mub[slot3];         // row yu + 1
-        const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) / T(12);
-        const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) / T(12);
+        const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) * T(1.0 / 12.0);
+        const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) * T(1.0 / 12.0);
         const T lap1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
-                        (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) / T(6);
-        const T gx0 = (T(4) * (q0[i + 1] - q0[i - 1]) + (qp[i + 1] - qp[i - 1] + qm[i + 1] - qm[i - 1])) / T(12);
-        const T gy0 = (T(4) * (qp[i] - qm[i]) + (qp[i + 1] - qm[i + 1] + qp[i - 1] - qm[i - 1])) / T(12);
+                        (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
+        const T gx0 = (T(4) * (q0[i + 1] - q0[i - 1]) + (qp[i + 1] - qp[i - 1] + qm[i + 1] - qm[i - 1])) * T(1.0 / 12.0);
+        const T gy0 = (T(4) * (qp[i] - qm[i]) + (qp[i + 1] - qm[i + 1] + qp[i - 1] - qm[i - 1])) * T(1.0 / 12.0);
         const T lap0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
-                        (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) / T(6);
-        const T gmx = (T(4) * (m0[j + 1] - m0[j - 1]) + (mp[j + 1] - mp[j - 1] + mm[j + 1] - mm[j - 1])) / T(12);
-        const T gmy = (T(4) * (mp[j] - mm[j]) + (mp[j + 1] - mm[j + 1] + mp[j - 1] - mm[j - 1])) / T(12);
+                        (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
+        const T gmx = (T(4) * (m0[j + 1] - m0[j - 1]) + (mp[j + 1] - mp[j - 1] + mm[j + 1] - mm[j - 1])) * T(1.0 / 12.0);
+        const T gmy = (T(4) * (mp[j] - mm[j]) + (mp[j + 1] - mm[j + 1] + mp[j - 1] - mm[j - 1])) * T(1.0 / 12.0);
         T dpx = T(0), dpy = T(0);
         if constexpr (HAS_S) {
             if (dS) {
                 const T* sm = sh.psi[(r + 1) % 3];
                 const T* s0 = sh.psi[(r + 2) % 3];
                 const T* sp = sh.psi[slot3];
-                dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) / T(12);
-                dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) / T(12);
+                dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) * T(1.0 / 12.0);
+                dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
         }
-        node_update<T, MODE>(d, dS, idu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
-                             gmy, dpx, dpy, fU, gp, lAx, lAy, lB, lCxx, lCyy, lCxy, cur, mom_out);
+        node_update<T, MODE>(d, K, dS, idu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
+                             gmy, dpx, dpy, fU, gpl, lAx, lAy, lB, lCxx, lCyy, lCxy, cur, mom_out);
     }
 }
 
 template <typename T, int CH, bool HAS_S, int MODE>
-__global__ void __launch_bounds__(64)
-strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
-             int step_offset, double* __restrict__ mom_out) {
+__device__ __forceinline__ void strip_body(const DomDev* __restrict__ doms, const int4* __restrict__ tiles,
+                                           int ntiles, int step_offset, double* __restrict__ mom_out) {
     __shared__ StripShared<T, HAS_S> sh;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= ntiles) return;
     const int4 tile = tiles[t];
     const DomDev& d = doms[tile.x];
     if (!d.live && MODE == kModeStep) return;
+    const KConst<T> K = kconst<T>(d);
     const int cur = (d.parity + step_offset) & 1;
     const bool dS = HAS_S && d.has_s;
     const int lane = threadIdx.x;
@@ -433,11 +433,209 @@ strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, in
     // (the row loaded two iterations earlier)
     constexpr int R = CH + 4;
     for (int r = 0; r < R; r += 3) {
-        strip_iter<T, CH, HAS_S, MODE>(d, sh, r, tile.y, tile.z, lane, cur, dS, F0, F1, mom_out);
+        strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r, tile.y, tile.z, lane, cur, dS, F0, F1, mom_out);
         if (r + 1 < R)
-            strip_iter<T, CH, HAS_S, MODE>(d, sh, r + 1, tile.y, tile.z, lane, cur, dS, F1, F2, mom_out);
+            strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 1, tile.y, tile.z, lane, cur, dS, F1, F2, mom_out);
         if (r + 2 < R)
-            strip_iter<T, CH, HAS_S, MODE>(d, sh, r + 2, tile.y, tile.z, lane, cur, dS, F2, F0, mom_out);
+            strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 2, tile.y, tile.z, lane, cur, dS, F2, F0, mom_out);
+    }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE>
+__global__ void __launch_bounds__(64)
+strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+             int step_offset, double* __restrict__ mom_out) {
+    strip_body<T, CH, HAS_S, MODE>(doms, tiles, ntiles, step_offset, mom_out);
+}
+
+// Same kernel compiled for five wavefronts per SIMD (fewer registers, a few
+// spilled to scratch): more rows in flight per compute unit.
+template <typename T, int CH, bool HAS_S, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
+strip_kernel_o5(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+                int step_offset, double* __restrict__ mom_out) {
+    strip_body<T, CH, HAS_S, MODE>(doms, tiles, ntiles, step_offset, mom_out);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined strip kernel: one wavefront per (domain, 60-column strip, CH-row
+// chunk).  Lane l covers column x0 - 2 + l (64 columns); lanes 2..61 update,
+// the two outer lanes on each side only supply the stencil halo, so all lanes
+// run the same instructions.  Each iteration r
+//   1. issues the loads of the next row (CH populations, phi0) and of the NS
+//      populations and lagged fields of the next row to update,
+//   2. sums the CH populations loaded one iteration earlier into phi1 (LDS),
+//   3. computes mubar1 one row above,
+//   4. updates the row two above with operands that are already in registers,
+// so the memory latency of step 1 overlaps a full iteration of arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T, bool HAS_S>
+struct Strip2Shared {
+    T phi0[5][64];
+    T phi1[5][64];
+    T mub[3][64];
+    T psi[HAS_S ? 3 : 1][64];
+};
+
+template <typename T>
+struct RowPre {
+    T g[9];
+    T lAx, lAy, lB, lCxx, lCyy, lCxy;
+};
+
+template <typename T, bool HAS_S>
+__device__ __forceinline__ void strip2_prefetch(const DomDev& d, int r, int x0, int y0, int CH, int lane,
+                                                int cur, bool dS, T (&fP)[9], T& ph0P, RowPre<T>& gP) {
+    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
+    const int N = nx * ny;
+    // CH populations and phi0 of row y0 - 2 + r (issued one iteration ahead)
+    const int yr = y0 - 2 + r;
+    const int sy = map_index(yr, ny, py);
+    const int sx = map_index(x0 - 2 + lane, nx, px);
+    pull9(gpc<T>(d.f[cur]), sx, sy, nx, ny, px, py, N, fP);
+    ph0P = gpc<T>(d.phi0)[sy * nx + sx];
+    // NS populations and lagged fields of the row updated in iteration r
+    const int yu = yr - 2;
+    const int x = x0 - 2 + lane;
+    if (r >= 4 && r < CH + 4 && yu < ny && lane >= 2 && lane < 62 && x < nx) {
+        const int idu = yu * nx + x;
+        pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gP.g);
+        gP.lAx = gpc<T>(d.lagA)[idu];
+        gP.lAy = gpc<T>(d.lagA)[N + idu];
+        gP.lB = gpc<T>(d.lagB)[idu];
+        if (HAS_S && dS) {
+            gP.lCxx = gpc<T>(d.lagC)[idu];
+            gP.lCyy = gpc<T>(d.lagC)[N + idu];
+            gP.lCxy = gpc<T>(d.lagC)[2 * N + idu];
+        }
+    }
+}
+
+template <typename T, bool HAS_S, int MODE>
+__device__ __forceinline__ void strip2_iter(const DomDev& d, const KConst<T>& K, Strip2Shared<T, HAS_S>& sh,
+                                            int r, int x0, int y0, int CH, int lane, int cur, bool dS,
+                                            T (&fS)[9], T (&fP)[9], T (&fU)[9], T& ph0S, T& ph0P,
+                                            RowPre<T>& gU, RowPre<T>& gP, double* __restrict__ mom_out) {
+    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
+    const int N = nx * ny;
+    const int yr = y0 - 2 + r;
+    // 1. loads for the next iteration
+    if (r + 1 < CH + 4) strip2_prefetch<T, HAS_S>(d, r + 1, x0, y0, CH, lane, cur, dS, fP, ph0P, gP);
+
+    // 2. phi0, phi1 of row yr from the operands loaded in the previous iteration
+    const int slot5 = r % 5;
+    {
+        T s = fS[0];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) s += fS[q];
+        sh.phi1[slot5][lane] = s;
+        sh.phi0[slot5][lane] = ph0S;
+    }
+    __syncthreads();
+
+    // 3. mubar1 (and psi) of row yr - 1 on lanes 1..62
+    const int slot3 = r % 3;
+    if (r >= 2) {
+        if (lane >= 1 && lane < 63) {
+            const int i = lane;
+            const T* pm = sh.phi1[(r + 3) % 5];
+            const T* p0 = sh.phi1[(r + 4) % 5];
+            const T* pp = sh.phi1[slot5];
+            const T* qm = sh.phi0[(r + 3) % 5];
+            const T* q0 = sh.phi0[(r + 4) % 5];
+            const T* qp = sh.phi0[slot5];
+            const T l1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
+                          (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
+            const T l0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
+                          (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
+            T mu0, mu1, mu2;
+            sh.mub[slot3][i] = mubar1<T>(K, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
+        }
+        if constexpr (HAS_S) {
+            if (dS) {
+                const int sx = map_index(x0 - 2 + lane, nx, px);
+                const int sy = map_index(yr - 1, ny, py);
+                sh.psi[slot3][lane] = gpc<T>(d.psi[cur])[sy * nx + sx];
+            }
+        }
+    }
+    __syncthreads();
+
+    // 4. update row yu = yr - 2 on lanes 2..61
+    const int yu = yr - 2;
+    const int x = x0 - 2 + lane;
+    if (r >= 4 && yu < ny && lane >= 2 && lane < 62 && x < nx) {
+        const int i = lane, j = lane;
+        const T* pm = sh.phi1[(r + 2) % 5];
+        const T* p0 = sh.phi1[(r + 3) % 5];
+        const T* pp = sh.phi1[(r + 4) % 5];
+        const T* qm = sh.phi0[(r + 2) % 5];
+        const T* q0 = sh.phi0[(r + 3) % 5];
+        const T* qp = sh.phi0[(r + 4) % 5];
+        const T* mm = sh.mub[(r + 1) % 3];
+        const T* m0 = sh.mub[(r + 2) % 3];
+        const T* mp = sh.mub[slot3];
+        const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) * T(1.0 / 12.0);
+        const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) * T(1.0 / 12.0);
+        const T lap1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
+                        (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
+        const T gx0 = (T(4) * (q0[i + 1] - q0[i - 1]) + (qp[i + 1] - qp[i - 1] + qm[i + 1] - qm[i - 1])) * T(1.0 / 12.0);
+        const T gy0 = (T(4) * (qp[i] - qm[i]) + (qp[i + 1] - qm[i + 1] + qp[i - 1] - qm[i - 1])) * T(1.0 / 12.0);
+        const T lap0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
+                        (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
+        const T gmx = (T(4) * (m0[j + 1] - m0[j - 1]) + (mp[j + 1] - mp[j - 1] + mm[j + 1] - mm[j - 1])) * T(1.0 / 12.0);
+        const T gmy = (T(4) * (mp[j] - mm[j]) + (mp[j + 1] - mm[j + 1] + mp[j - 1] - mm[j - 1])) * T(1.0 / 12.0);
+        T dpx = T(0), dpy = T(0);
+        if constexpr (HAS_S) {
+            if (dS) {
+                const T* sm = sh.psi[(r + 1) % 3];
+                const T* s0 = sh.psi[(r + 2) % 3];
+                const T* sp = sh.psi[slot3];
+                dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) * T(1.0 / 12.0);
+                dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
+            }
+        }
+        node_update<T, MODE>(d, K, dS, yu * nx + x, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
+                             gmx, gmy, dpx, dpy, fU, gU.g, gU.lAx, gU.lAy, gU.lB, gU.lCxx, gU.lCyy, gU.lCxy,
+                             cur, mom_out);
+    }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE>
+__global__ void __launch_bounds__(64)
+strip2_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+              int step_offset, double* __restrict__ mom_out) {
+    __shared__ Strip2Shared<T, HAS_S> sh;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int4 tile = tiles[t];
+    const DomDev& d = doms[tile.x];
+    if (!d.live && MODE == kModeStep) return;
+    const KConst<T> K = kconst<T>(d);
+    const int cur = (d.parity + step_offset) & 1;
+    const bool dS = HAS_S && d.has_s;
+    const int lane = threadIdx.x;
+    const int x0 = tile.y, y0 = tile.z;
+    T F0[9], F1[9], F2[9], F3[9];
+    T P0 = T(0), P1 = T(0);
+    RowPre<T> G0, G1;
+    G0.lCxx = G0.lCyy = G0.lCxy = G1.lCxx = G1.lCyy = G1.lCxy = T(0);
+    // prologue: operands of iteration 0
+    strip2_prefetch<T, HAS_S>(d, 0, x0, y0, CH, lane, cur, dS, F0, P0, G0);
+    // iteration r sums F[r % 4], prefetches into F[(r + 1) % 4], updates with
+    // F[(r + 2) % 4] (loaded for row r - 2); G and P alternate
+    constexpr int R = CH + 4;
+    for (int r = 0; r < R; r += 4) {
+        strip2_iter<T, HAS_S, MODE>(d, K, sh, r, x0, y0, CH, lane, cur, dS, F0, F1, F2, P0, P1, G0, G1, mom_out);
+        if (r + 1 < R)
+            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 1, x0, y0, CH, lane, cur, dS, F1, F2, F3, P1, P0, G1, G0,
+                                        mom_out);
+        if (r + 2 < R)
+            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 2, x0, y0, CH, lane, cur, dS, F2, F3, F0, P0, P1, G0, G1,
+                                        mom_out);
+        if (r + 3 < R)
+            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 3, x0, y0, CH, lane, cur, dS, F3, F0, F1, P1, P0, G1, G0,
+                                        mom_out);
     }
 }
 
@@ -450,7 +648,7 @@ __global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const doub
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
     const int x = id % nx, y = id / nx;
-    const T* phi0 = (const T*)d.phi0;
+    gptr<const T> phi0 = gpc<T>(d.phi0);
     T v0[9], v1[9];
     int k = 0;
     for (int dy = -1; dy <= 1; ++dy)
@@ -462,31 +660,32 @@ __global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const doub
     // row-major 3x3 neighbourhood, centre at index 4, pitch 3
     const T lap0 = lap9(v0, 4, 3), lap1 = lap9(v1, 4, 3);
     T mu0, mu1, mu2;
-    const T mub = mubar1<T>(d, v0[4], v1[4], lap0, lap1, mu0, mu1, mu2);
-    const T c2 = T(d.c2), w0 = T(d.w0);
+    const KConst<T> K = kconst<T>(d);
+    const T mub = mubar1<T>(K, v0[4], v1[4], lap0, lap1, mu0, mu1, mu2);
+    const T c2 = K.c2, w0 = K.w0;
     const T w1 = (c2 - c2 * c2) * T(0.5), w5 = c2 * c2 * T(0.25);
-    const T emu = T(d.eta) * mub;
+    const T emu = K.eta * mub;
     const int par = d.parity;
-    T* f = (T*)d.f[par];
-    T* g = (T*)d.g[par];
+    gptr<T> f = gp<T>(d.f[par]);
+    gptr<T> g = gp<T>(d.g[par]);
     f[id] = v1[4] + (w0 - T(1)) * emu;
     for (int q = 1; q <= 4; ++q) f[q * N + id] = w1 * emu;
     for (int q = 5; q <= 8; ++q) f[q * N + id] = w5 * emu;
-    g[id] = T(d.gauge);
+    g[id] = K.gauge;
     for (int q = 1; q < 9; ++q) g[q * N + id] = T(0);
-    T* A = (T*)d.lagA;
+    gptr<T> A = gp<T>(d.lagA);
     A[id] = T(0);
     A[N + id] = T(0);
-    ((T*)d.lagB)[id] = T(0);
+    gp<T>(d.lagB)[id] = T(0);
     if (d.has_s) {
-        T* C = (T*)d.lagC;
-        C[id] = T(0);
-        C[N + id] = T(0);
-        C[2 * N + id] = T(0);
-        ((T*)d.psi[0])[id] = T(0);
-        ((T*)d.psi[1])[id] = T(0);
+        gptr<T> Cl = gp<T>(d.lagC);
+        Cl[id] = T(0);
+        Cl[N + id] = T(0);
+        Cl[2 * N + id] = T(0);
+        gp<T>(d.psi[0])[id] = T(0);
+        gp<T>(d.psi[1])[id] = T(0);
     }
-    d.snap[id] = __builtin_nan("");
+    gp<double>(d.snap)[id] = __builtin_nan("");
 }
 
 // ---------------------------------------------------------------------------
@@ -522,7 +721,8 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
     const int dom = dom_list[blockIdx.y];
     const DomDev& d = doms[dom];
     const int nx = d.nx, ny = d.ny, N = nx * ny;
-    const T* fin = (const T*)d.f[d.parity];
+    gptr<const T> fin = gpc<T>(d.f[d.parity]);
+    gptr<double> snap = gp<double>(d.snap);
     CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
     double bad = 0.0;
     for (int y = blockIdx.x; y < ny; y += gridDim.x) {
@@ -535,9 +735,9 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
             if (!isfinite(v)) bad += 1.0;
             csum_add(m, v);
             csum_add(n2, v * v);
-            const double prev = d.snap[id];
+            const double prev = snap[id];
             if (isfinite(prev)) csum_add(r, (v - prev) * (v - prev));
-            if (update_snap) d.snap[id] = v;
+            if (update_snap) snap[id] = v;
         }
     }
     __shared__ double sh[7][kRedThreads];
@@ -591,8 +791,8 @@ template <typename T>
 __global__ void export_populations(const DomDev* __restrict__ doms, int dom, double* __restrict__ out) {
     const DomDev& d = doms[dom];
     const int N = d.nx * d.ny;
-    const T* f = (const T*)d.f[d.parity];
-    const T* g = (const T*)d.g[d.parity];
+    gptr<const T> f = gpc<T>(d.f[d.parity]);
+    gptr<const T> g = gpc<T>(d.g[d.parity]);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 9 * N; i += gridDim.x * blockDim.x) {
         out[i] = double(f[i]);
         out[9 * N + i] = double(g[i]);

@@ -229,25 +229,31 @@ def solid_fraction(phi0: np.ndarray) -> float:
 # Batched sweep: droplets on random rough walls
 # ---------------------------------------------------------------------------
 def rough_wall_droplet(s, seed, theta_deg=None, D=4.0, sigma12=0.01, tau=0.8,
-                       base=24.0, n_modes=3, amp_max=4.0,
+                       base=24.0, n_modes=3, amp_max=4.0, max_mode=3,
                        name=None) -> DomainSpec:
     """Droplet of radius 0.2 s on a random rough wall h(x) = base + sum of sinusoids.
 
-    h(x) = base + sum_k a_k sin(2 pi n_k x / s + p_k), a_k ~ U[0, amp_max],
-    n_k ~ U{1..8}, p_k ~ U[0, 2 pi); contact angle ~ U[30, 150] deg unless given.
+    h(x) = base + sum_k a_k sin(2 pi n_k x / s + p_k), a_k ~ U[0, amp_max] (so the
+    amplitude is at most 12 cells), n_k ~ U{1..max_mode}, p_k ~ U[0, 2 pi); contact
+    angle ~ U[30, 150] deg unless given.  The solid field is a tanh of the
+    first-order normal distance (y - h)/sqrt(1 + h'^2), so the diffuse wall keeps
+    the width D normal to the surface also where the wall is steep.
     Periodic in x (the wall is s-periodic), walls in y.
     """
     rng = np.random.default_rng(seed)
     a = rng.uniform(0.0, amp_max, n_modes)
-    nk = rng.integers(1, 9, n_modes)
+    nk = rng.integers(1, max_mode + 1, n_modes)
     ph = rng.uniform(0.0, 2.0 * math.pi, n_modes)
     th = rng.uniform(30.0, 150.0) if theta_deg is None else theta_deg
     x, y = _grid(s, s)
-    h = base + sum(a[k] * np.sin(2.0 * math.pi * nk[k] * x / s + ph[k]) for k in range(n_modes))
-    phi0 = 0.5 - 0.5 * np.tanh(2.0 * (y - h) / D)
+    k = 2.0 * math.pi * nk / s
+    h = base + sum(a[i] * np.sin(k[i] * x + ph[i]) for i in range(n_modes))
+    dh = sum(a[i] * k[i] * np.cos(k[i] * x + ph[i]) for i in range(n_modes))
+    dist = (y - h) / np.sqrt(1.0 + dh * dh)
+    phi0 = 0.5 - 0.5 * np.tanh(2.0 * dist / D)
     R0 = 0.2 * s
     xc = s / 2.0
-    hc = base + sum(a[k] * math.sin(2.0 * math.pi * nk[k] * xc / s + ph[k]) for k in range(n_modes))
+    hc = base + sum(a[i] * math.sin(k[i] * xc + ph[i]) for i in range(n_modes))
     phi1 = (1.0 - phi0) * _tanh_step(R0 - np.hypot(x - xc, y - hc), D)
     nu = (tau - 0.5) * 0.5
     return DomainSpec(nx=s, ny=s, phi0=phi0, phi1=phi1, periodic_x=1, periodic_y=0,

@@ -1,0 +1,254 @@
+"""Batched sweep, surrogate training and the learned warm start.
+
+1. ``sweep``: many independent rough-wall droplet domains advance together in
+   the batched launcher until each one's residual drops below a tolerance (or
+   a step cap); their equilibrium phase fields become training data.
+2. ``train``: the encoder-decoder of ``surrogate.py`` learns phi1 from (phi0,
+   contact angle, volume) on 256 x 256 resamplings, with x-mirror augmentation
+   (the problem is symmetric under x -> -x).
+3. ``evaluate``: on held-out geometries, the time to reach the tolerance from
+   the plain initial condition is compared with the time for inference +
+   mass-projected warm start + relaxation; a warm start that fails (non-finite
+   values, or the step cap) falls back to the plain initial condition.
+
+All LB and network arithmetic runs in the HIP libraries; this module is
+orchestration (timing with device synchronisation, bookkeeping).
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import geometry as G
+from .lbm import Context, TPF_ENAN, TPF_OK
+from . import surrogate as S
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def sweep(specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int, precision: int = 32,
+          tile: Optional[int] = None, log=print) -> Dict:
+    """Advances all domains in one context to r < tol; returns fields and statistics."""
+    ctx = Context(precision=precision)
+    for s in specs:
+        ctx.add_domain(s)
+    ctx.finalize()
+    if tile:
+        ctx.set_tile(tile)
+    _sync()
+    t0 = time.perf_counter()
+    rc, steps = ctx.run_to_residual(tol, check_every=check_every, max_steps=max_steps)
+    _sync()
+    wall = time.perf_counter() - t0
+    phi = []
+    status = []
+    res = []
+    for i in range(len(specs)):
+        d = ctx.diag(i)
+        status.append(d["status"])
+        res.append(d["residual"])
+        phi.append(ctx.moments(i)[0])
+    nodes = sum(s.nx * s.ny for s in specs)
+    node_steps = float(sum(int(steps[i]) * specs[i].nx * specs[i].ny for i in range(len(specs))))
+    out = {"phi1": phi, "steps": steps, "status": np.array(status), "residual": np.array(res),
+           "wall_s": wall, "rc": rc, "nodes": nodes, "mlups": node_steps / wall / 1e6}
+    ctx.close()
+    return out
+
+
+def build_dataset(specs: List[G.DomainSpec], phi_eq: List[np.ndarray], status) -> Dict[str, np.ndarray]:
+    """Network inputs/targets on the 256 x 256 grid (GPU bilinear resampling)."""
+    X0, TH, VOL, Y = [], [], [], []
+    for s, phi, st in zip(specs, phi_eq, status):
+        if st == TPF_ENAN or not np.isfinite(phi).all():
+            continue
+        f0 = S.resample(s.phi0[None], S.RES, S.RES)[0]
+        f1 = S.resample(phi[None], S.RES, S.RES)[0]
+        X0.append(f0)
+        TH.append(s.theta_deg)
+        VOL.append(S.volume_feature(s.phi1))
+        Y.append(np.clip(f1, 0.0, 1.0))
+    return {"phi0": np.array(X0, np.float32), "theta": np.array(TH, np.float32),
+            "vol": np.array(VOL, np.float32), "target": np.array(Y, np.float32)}
+
+
+def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: float = 1e-3, seed: int = 0,
+          log=print, time_budget_s: float = 1e9) -> S.UNet:
+    import torch
+    net = S.UNet(seed=seed)
+    n = len(data["theta"])
+    rng = np.random.default_rng(seed)
+    t0 = time.perf_counter()
+    hist = []
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        losses = []
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            phi0 = data["phi0"][idx]
+            tgt = data["target"][idx]
+            flip = rng.random(batch) < 0.5
+            phi0 = np.where(flip[:, None, None], phi0[:, :, ::-1], phi0)
+            tgt = np.where(flip[:, None, None], tgt[:, :, ::-1], tgt)
+            net.pack(np.ascontiguousarray(phi0), data["theta"][idx], data["vol"][idx])
+            t = torch.tensor(np.ascontiguousarray(tgt).ravel(), device=net.dev)
+            losses.append(net.train_step(batch, t, lr=lr).clone())
+        ep_loss = float(torch.stack(losses).mean().item()) if losses else float("nan")
+        hist.append(ep_loss)
+        log(json.dumps({"epoch": ep, "loss": ep_loss, "t": round(time.perf_counter() - t0, 1)}))
+        if time.perf_counter() - t0 > time_budget_s:
+            break
+    net.history = hist
+    return net
+
+
+def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int,
+             precision: int = 32, log=print) -> Dict:
+    """Plain vs learned time to r < tol on the same held-out domains (batched)."""
+    # plain
+    plain = sweep(specs, tol, check_every, max_steps, precision=precision)
+    log(json.dumps({"plain_wall_s": round(plain["wall_s"], 3), "plain_rc": plain["rc"],
+                    "plain_steps_mean": float(np.mean(plain["steps"]))}))
+    # learned: inference + warm start + relaxation
+    ctx = Context(precision=precision)
+    for s in specs:
+        ctx.add_domain(s)
+    ctx.finalize()
+    _sync()
+    t0 = time.perf_counter()
+    B = 32
+    preds = []
+    for b0 in range(0, len(specs), B):
+        grp = specs[b0:b0 + B]
+        phi0 = np.stack([S.resample(s.phi0[None], S.RES, S.RES)[0] for s in grp])
+        th = np.array([s.theta_deg for s in grp], np.float32)
+        vol = np.array([S.volume_feature(s.phi1) for s in grp], np.float32)
+        preds.extend(list(net.predict(phi0, th, vol)))
+    fallback = 0
+    for i, s in enumerate(specs):
+        try:
+            f = S.warm_start_field(preds[i], s.phi0, float(np.sum(s.phi1)))
+        except ValueError:
+            f = s.phi1
+            fallback += 1
+        ctx.set_phi1(i, f)
+    _sync()
+    t_inf = time.perf_counter() - t0
+    rc, steps = ctx.run_to_residual(tol, check_every=check_every, max_steps=max_steps)
+    # fallback: domains whose warm start failed (non-finite values) restart from
+    # the plain initial condition
+    bad = [i for i in range(len(specs)) if ctx.diag(i)["status"] == TPF_ENAN]
+    for i in bad:
+        ctx.set_phi1(i, specs[i].phi1)
+    if bad:
+        fallback += len(bad)
+        rc, steps2 = ctx.run_to_residual(tol, check_every=check_every, max_steps=max_steps)
+        steps = steps + steps2
+    _sync()
+    t_learn = time.perf_counter() - t0
+    phi_l = [ctx.moments(i)[0] for i in range(len(specs))]
+    ctx.close()
+    # surrogate error against the plain equilibrium
+    err = []
+    for i, s in enumerate(specs):
+        pe = plain["phi1"][i]
+        f = S.warm_start_field(preds[i], s.phi0, float(np.sum(s.phi1)))
+        err.append(float(np.linalg.norm(f - pe) / np.linalg.norm(pe)))
+    agree = [float(np.linalg.norm(phi_l[i] - plain["phi1"][i]) / np.linalg.norm(plain["phi1"][i]))
+             for i in range(len(specs))]
+    ps = np.array(plain["steps"], dtype=float)
+    ls = np.array(steps, dtype=float)
+    out = {"domains": len(specs), "tol": tol, "check_every": check_every, "cap": max_steps,
+           "plain_s": plain["wall_s"], "learned_s": t_learn, "inference_s": t_inf,
+           "speedup": plain["wall_s"] / t_learn,
+           "plain_steps_mean": float(ps.mean()), "learned_steps_mean": float(ls.mean()),
+           "steps_ratio_mean": float(ps.mean() / max(ls.mean(), 1.0)),
+           "plain_capped": int((ps >= max_steps).sum()), "learned_capped": int((ls >= max_steps).sum()),
+           "fallbacks": fallback, "surrogate_rel_l2_mean": float(np.mean(err)),
+           "final_state_rel_l2_max": float(np.max(agree))}
+    log(json.dumps(out))
+    return out
+
+
+def save_params(net: S.UNet, path: str):
+    p = net.params_numpy()
+    flat = {}
+    for k, (w, b) in p.items():
+        flat[k + ".w"] = w.astype(np.float32)
+        flat[k + ".b"] = b.astype(np.float32)
+    np.savez_compressed(path, **flat)
+
+
+def load_params(path: str):
+    z = np.load(path)
+    names = sorted({k.rsplit(".", 1)[0] for k in z.files})
+    return {k: (z[k + ".w"].astype(np.float64), z[k + ".b"].astype(np.float64)) for k in names}
+
+
+def main(argv=None):
+    import argparse
+    import os
+    ap = argparse.ArgumentParser(description="batched sweep -> surrogate training -> warm-start evaluation")
+    ap.add_argument("--train-domains", type=int, default=512)
+    ap.add_argument("--smin", type=int, default=128)
+    ap.add_argument("--smax", type=int, default=512)
+    ap.add_argument("--eval-domains", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--sweep-cap", type=int, default=60000)
+    ap.add_argument("--eval-cap", type=int, default=100000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--train-budget-s", type=float, default=240.0)
+    ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")
+    ap.add_argument("--out", default="gpurun_out/warmstart")
+    args = ap.parse_args(argv)
+    os.makedirs(args.out, exist_ok=True)
+    logf = open(os.path.join(args.out, "log.jsonl"), "a")
+
+    def log(msg):
+        print(msg, flush=True)
+        logf.write(msg + "\n")
+        logf.flush()
+
+    result = {"config": vars(args)}
+    if args.weights:
+        net = S.UNet(params=load_params(args.weights))
+    else:
+        specs = G.batched_sweep(n_domains=args.train_domains, smin=args.smin, smax=args.smax)
+        log(json.dumps({"phase": "sweep", "domains": len(specs), "nodes": sum(s.nx * s.ny for s in specs)}))
+        sw = sweep(specs, args.tol, args.check_every, args.sweep_cap)
+        conv = int(np.sum(np.array(sw["steps"]) < args.sweep_cap))
+        result["sweep"] = {"wall_s": sw["wall_s"], "mlups": sw["mlups"], "nodes": sw["nodes"],
+                           "converged": conv, "nan": int(np.sum(sw["status"] == TPF_ENAN)),
+                           "steps_mean": float(np.mean(sw["steps"]))}
+        log(json.dumps({"phase": "sweep_done", **result["sweep"]}))
+        data = build_dataset(specs, sw["phi1"], sw["status"])
+        del sw
+        log(json.dumps({"phase": "train", "samples": int(len(data["theta"]))}))
+        net = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
+                    time_budget_s=args.train_budget_s)
+        result["train"] = {"samples": int(len(data["theta"])), "loss_first": net.history[0],
+                           "loss_last": net.history[-1], "epochs": len(net.history),
+                           "params": net.n_params(), "gflop_fwd_per_sample": net.flops_per_sample() / 1e9}
+        save_params(net, os.path.join(args.out, "unet_weights.npz"))
+        log(json.dumps({"phase": "train_done", **result["train"]}))
+    held = G.held_out_set(n_domains=args.eval_domains, s=256)
+    log(json.dumps({"phase": "evaluate", "domains": len(held)}))
+    result["evaluate"] = evaluate(net, held, args.tol, args.check_every, args.eval_cap, log=log)
+    with open(os.path.join(args.out, "result.json"), "w") as f:
+        json.dump(result, f, indent=1, default=float)
+    log(json.dumps({"phase": "done", "speedup": result["evaluate"]["speedup"]}))
+    return result
+
+
+if __name__ == "__main__":
+    main()

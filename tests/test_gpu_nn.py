@@ -1,0 +1,268 @@
+"""Parity of the surrogate's HIP kernels (BF16 matrix cores, FP32 accumulation)
+with the FP64 numpy oracle, run on an MI355X.
+
+Inputs are rounded to bf16 before both sides see them, so the oracle computes
+the exact result of the same operands; the remaining differences are FP32
+accumulation order and the final bf16 rounding of activations (relative
+2^-8), which set the tolerances."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nn as O
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(11)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# device tensors handed to the kernels as raw pointers must outlive the call:
+# every helper keeps a reference here (cleared per test)
+_KEEP = []
+
+
+@pytest.fixture(autouse=True)
+def _keep_alive():
+    yield
+    _torch().cuda.synchronize()
+    _KEEP.clear()
+
+
+def _bf16_dev(a):
+    torch = _torch()
+    bits = O.to_bf16_bits(a).view(np.int16)
+    t = torch.tensor(bits, device="cuda").view(torch.bfloat16)
+    _KEEP.append(t)
+    return t
+
+
+def _from_dev_bf16(t, shape):
+    torch = _torch()
+    bits = t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return O.from_bf16_bits(bits).reshape(shape)
+
+
+def _f32_dev(a):
+    t = _torch().tensor(np.asarray(a, np.float32), device="cuda")
+    _KEEP.append(t)
+    return t
+
+
+def _lib():
+    from paper_2311_05091_amd.surrogate import nnlib
+    return nnlib()
+
+
+def _p(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_mfma_operand_layout():
+    """Small integers are exact in bf16 and FP32: the 16x32 by 32x16 product must be exact."""
+    _say("mfma selftest")
+    torch = _torch()
+    A = rng.integers(-4, 5, size=(16, 32)).astype(np.float32)
+    B = rng.integers(-4, 5, size=(32, 16)).astype(np.float32)
+    D = torch.zeros(256, dtype=torch.float32, device="cuda")
+    assert _lib().tpfnn_mfma_selftest(_p(_bf16_dev(A)), _p(_bf16_dev(B)), _p(D), None) == 0
+    assert np.array_equal(D.cpu().numpy().reshape(16, 16), A @ B)
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout,relu", [(2, 16, 16, 32, 32, 1), (1, 8, 16, 64, 128, 0),
+                                                 (3, 32, 8, 96, 64, 1), (1, 16, 8, 256, 256, 1)])
+def test_conv_forward(N, H, W, Cin, Cout, relu):
+    _say("conv fwd", N, H, W, Cin, Cout)
+    torch = _torch()
+    x = O.bf16_round(rng.normal(size=(N, H, W, Cin)))
+    w = O.bf16_round(rng.normal(size=(Cout, 3, 3, Cin)) / np.sqrt(9 * Cin))
+    b = rng.normal(size=Cout).astype(np.float32).astype(np.float64)
+    y = torch.empty(N * H * W * Cout, dtype=torch.bfloat16, device="cuda")
+    rc = _lib().tpfnn_conv3x3_fwd(_p(_bf16_dev(x)), N, H, W, Cin, _p(_bf16_dev(w)), _p(_f32_dev(b)), Cout,
+                                  relu, _p(y), None)
+    assert rc == 0
+    ref = O.conv3x3(x, w, b)
+    if relu:
+        ref = O.relu(ref)
+    got = _from_dev_bf16(y, ref.shape)
+    err = np.abs(got - ref)
+    assert np.all(err <= 2 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+def test_conv_input_gradient_via_flipped_weights():
+    N, H, W, Cin, Cout = 2, 16, 8, 64, 32
+    _say("dgrad")
+    torch = _torch()
+    dy = O.bf16_round(rng.normal(size=(N, H, W, Cout)))
+    w = O.bf16_round(rng.normal(size=(Cout, 3, 3, Cin)) / np.sqrt(9 * Cin))
+    wt = torch.empty(w.size, dtype=torch.bfloat16, device="cuda")
+    dx = torch.empty(N * H * W * Cin, dtype=torch.bfloat16, device="cuda")
+    lib = _lib()
+    assert lib.tpfnn_weight_flip(_p(_bf16_dev(w)), Cout, Cin, _p(wt), None) == 0
+    assert lib.tpfnn_conv3x3_fwd(_p(_bf16_dev(dy)), N, H, W, Cout, _p(wt), None, Cin, 0, _p(dx), None) == 0
+    ref = O.conv3x3_dx(dy, w)
+    got = _from_dev_bf16(dx, ref.shape)
+    assert np.all(np.abs(got - ref) <= 2 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 64), (1, 32, 32, 64, 32), (4, 8, 8, 128, 256)])
+def test_conv_weight_gradient(N, H, W, Cin, Cout):
+    _say("wgrad", N, H, W, Cin, Cout)
+    torch = _torch()
+    lib = _lib()
+    x = O.bf16_round(rng.normal(size=(N, H, W, Cin)))
+    dy = O.bf16_round(rng.normal(size=(N, H, W, Cout)))
+    ws = lib.tpfnn_wgrad_workspace(N, H, W, Cin, Cout)
+    work = torch.empty(int(ws), dtype=torch.uint8, device="cuda")
+    dw = torch.empty(Cout * 9 * Cin, dtype=torch.float32, device="cuda")
+    db = torch.empty(Cout, dtype=torch.float32, device="cuda")
+    rc = lib.tpfnn_conv3x3_wgrad(_p(_bf16_dev(x)), _p(_bf16_dev(dy)), N, H, W, Cin, Cout, _p(dw), _p(db), _p(work),
+                                 work.numel(), None)
+    assert rc == 0
+    ref = O.conv3x3_dw(x, dy)
+    got = dw.cpu().numpy().reshape(ref.shape)
+    scale = np.sqrt(N * H * W)
+    assert np.abs(got - ref).max() <= 1e-5 * scale
+    assert np.allclose(db.cpu().numpy(), dy.reshape(-1, Cout).sum(0), atol=1e-4 * scale)
+
+
+def test_pool_upsample_concat_split_exact():
+    _say("elementwise")
+    torch = _torch()
+    lib = _lib()
+    N, H, W, C = 2, 8, 16, 32
+    x = O.bf16_round(rng.normal(size=(N, H, W, C)))
+    y = torch.empty(N * H * W * C // 4, dtype=torch.bfloat16, device="cuda")
+    assert lib.tpfnn_avgpool2_fwd(_p(_bf16_dev(x)), N, H, W, C, _p(y), None) == 0
+    ref = O.bf16_round(O.avgpool2(x))
+    assert np.array_equal(_from_dev_bf16(y, ref.shape), ref)
+    u = torch.empty(N * H * W * C, dtype=torch.bfloat16, device="cuda")
+    assert lib.tpfnn_upsample2_fwd(_p(y), N, H // 2, W // 2, C, _p(u), None) == 0
+    assert np.array_equal(_from_dev_bf16(u, x.shape), O.upsample2(ref))
+    a = O.bf16_round(rng.normal(size=(N * H * W, 32)))
+    b = O.bf16_round(rng.normal(size=(N * H * W, 64)))
+    cat = torch.empty(N * H * W * 96, dtype=torch.bfloat16, device="cuda")
+    assert lib.tpfnn_concat(_p(_bf16_dev(a)), 32, _p(_bf16_dev(b)), 64, N * H * W, _p(cat), None) == 0
+    assert np.array_equal(_from_dev_bf16(cat, (N * H * W, 96)), np.concatenate([a, b], 1))
+    da = torch.empty(N * H * W * 32, dtype=torch.bfloat16, device="cuda")
+    dbb = torch.empty(N * H * W * 64, dtype=torch.bfloat16, device="cuda")
+    assert lib.tpfnn_split(_p(cat), 32, 64, N * H * W, _p(da), _p(dbb), None) == 0
+    assert np.array_equal(_from_dev_bf16(da, a.shape), a) and np.array_equal(_from_dev_bf16(dbb, b.shape), b)
+
+
+def test_head_loss_and_gradients():
+    _say("head")
+    torch = _torch()
+    lib = _lib()
+    npix, C = 4096, 32
+    x = O.bf16_round(rng.normal(size=(npix, C)) * 0.5)
+    w = rng.normal(size=C).astype(np.float32).astype(np.float64) * 0.3
+    b = np.array([0.1], np.float32).astype(np.float64)
+    t = rng.uniform(size=npix).astype(np.float32).astype(np.float64)
+    pred = torch.empty(npix, dtype=torch.float32, device="cuda")
+    dx = torch.empty(npix * C, dtype=torch.bfloat16, device="cuda")
+    dw = torch.empty(C, dtype=torch.float32, device="cuda")
+    db = torch.empty(1, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = lib.tpfnn_head_workspace(npix, C)
+    work = torch.empty(int(ws), dtype=torch.uint8, device="cuda")
+    rc = lib.tpfnn_head(_p(_bf16_dev(x)), npix, C, _p(_f32_dev(w)), _p(_f32_dev(b)), _p(pred), _p(_f32_dev(t)),
+                        _p(dx), _p(dw), _p(db), _p(loss), _p(work), work.numel(), None)
+    assert rc == 0
+    rp, rl, rdx, rdw, rdb = O.head(x, w, b[0], t)
+    assert np.abs(pred.cpu().numpy() - rp).max() < 1e-6
+    assert abs(loss.item() - rl) < 1e-6 * rl
+    assert np.abs(dw.cpu().numpy() - rdw).max() < 1e-6 * np.abs(rdw).max() + 1e-9
+    assert abs(db.item() - rdb) < 1e-6 * abs(rdb) + 1e-9
+    got_dx = _from_dev_bf16(dx, rdx.shape)
+    assert np.all(np.abs(got_dx - rdx) <= 2 ** -8 * np.abs(rdx) + 1e-12)
+
+
+def test_adam_and_resample():
+    _say("adam resample")
+    torch = _torch()
+    lib = _lib()
+    n = 1000
+    p, g = rng.normal(size=n), rng.normal(size=n)
+    m, v = rng.normal(size=n) * 0.1, rng.uniform(size=n) * 0.1
+    P, M, Vv, Gt = (_f32_dev(a) for a in (p, m, v, g))
+    assert lib.tpfnn_adam(_p(P), _p(M), _p(Vv), _p(Gt), None, n, 1e-3, 0.9, 0.999, 1e-8, 5, None) == 0
+    rp, rm, rv = O.adam(p.astype(np.float32).astype(np.float64), m.astype(np.float32), v.astype(np.float32),
+                        g.astype(np.float32), 1e-3, 0.9, 0.999, 1e-8, 5)
+    assert np.abs(P.cpu().numpy() - rp).max() < 1e-6
+    src = rng.uniform(size=(3, 37, 53))
+    from paper_2311_05091_amd.surrogate import resample
+    got = resample(src, 64, 29)
+    ref = O.resample(src.astype(np.float32).astype(np.float64), 64, 29)
+    assert np.abs(got - ref).max() < 1e-5
+
+
+def test_unet_forward_matches_oracle_and_gradients_are_consistent():
+    """Whole network at 256 x 256: the GPU prediction follows the FP64 oracle
+    (bf16 activations, so within a few percent), and the GPU gradient agrees
+    with a central finite difference of the FP64 oracle's loss along a random
+    direction in the weights of every layer."""
+    from paper_2311_05091_amd.surrogate import UNet, init_params, RES
+    _say("unet")
+    torch = _torch()
+    params = init_params(seed=5)
+    # bf16-representable weights so both sides start from the same model
+    params = {k: (O.bf16_round(w), b) for k, (w, b) in params.items()}
+    net = UNet(params=params)
+    N = 1
+    phi0 = np.zeros((N, RES, RES))
+    yy, xx = np.mgrid[0:RES, 0:RES]
+    phi0[0] = 0.5 - 0.5 * np.tanh((yy - 40) / 2.0)
+    target = (1 - phi0) * (0.5 + 0.5 * np.tanh((60 - np.hypot(xx - 128, yy - 40)) / 2.0))
+    th, vol = np.array([70.0]), np.array([0.9])
+    net.pack(phi0, th, vol)
+    pred = net.forward(N).reshape(RES, RES).cpu().numpy()
+    x = np.zeros((N, RES, RES, 32))
+    x[..., 0] = O.bf16_round(phi0)
+    x[..., 1] = O.bf16_round(np.full_like(phi0, (70.0 - 90.0) / 60.0))
+    x[..., 2] = O.bf16_round(np.full_like(phi0, 0.9))
+    acts = O.unet_forward(params, x)
+    ref = O.head(acts["last"], *params["head"])[0]
+    assert np.abs(pred - ref).max() < 3e-2
+    tgt = _f32_dev(target.ravel())
+    net.forward(N)
+    loss = net.loss_and_grads(N, tgt).item()
+    ref_loss = O.unet_loss(params, x, target)
+    assert abs(loss / ref_loss - 1) < 3e-2
+    # directional derivative along d (all 3x3 layers and the head)
+    d = {k: rng.normal(size=np.shape(w)) * (np.abs(w).mean() + 1e-3) for k, (w, b) in params.items()}
+    gd = 0.0
+    for k in d:
+        gd += float(np.sum(net.gw[k].cpu().numpy().reshape(np.shape(d[k])) * d[k]))
+    eps = 1e-3
+    pp = {k: (w + eps * d[k], b) for k, (w, b) in params.items()}
+    pm = {k: (w - eps * d[k], b) for k, (w, b) in params.items()}
+    fd = (O.unet_loss(pp, x, target) - O.unet_loss(pm, x, target)) / (2 * eps)
+    print("directional derivative gpu %.6e fd %.6e" % (gd, fd))
+    assert abs(gd - fd) <= 0.05 * abs(fd)
+
+
+def test_training_reduces_loss():
+    from paper_2311_05091_amd.surrogate import UNet, RES
+    _say("train")
+    torch = _torch()
+    net = UNet(seed=1)
+    N = 2
+    yy, xx = np.mgrid[0:RES, 0:RES]
+    phi0 = np.stack([0.5 - 0.5 * np.tanh((yy - h) / 2.0) for h in (30, 50)])
+    target = np.stack([(1 - phi0[i]) * (0.5 + 0.5 * np.tanh((r - np.hypot(xx - 128, yy - h)) / 2.0))
+                       for i, (h, r) in enumerate(((30, 50), (50, 70)))])
+    net.pack(phi0, np.array([60.0, 120.0]), np.array([0.8, 1.2]))
+    tgt = _f32_dev(target.ravel())
+    losses = [net.train_step(N, tgt, lr=2e-3).item() for _ in range(60)]
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.5 * losses[0]

@@ -63,23 +63,36 @@ def test_fp64_parity(orc, name, factory, steps):
     ctx.close()
 
 
-def test_every_tile_shape_identical(orc):
-    """The tile shape changes only the work decomposition, not a single bit."""
+def test_every_tile_shape_consistent(orc):
+    """The tile shape changes only the work decomposition: shapes served by the
+    same kernel agree bit for bit; the tile (codes 1-7), strip (8-11) and
+    pipelined strip (12-14) kernels may contract multiply-adds differently, so
+    across kernels they agree to rounding (FP32: 2e-6 of the largest
+    population after 40 steps; FP64: 1e-13)."""
     from paper_2311_05091_amd.lbm import tile_codes
     sp = G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0, rho=(1.0, 1.0, 0.1),
                           mu=(0.15, 0.15, 0.015))
     ref = {}
     for code, tx, ty in tile_codes():
         _say("tile", code, tx, ty)
+        fam = "tile" if code < 8 else ("strip" if code < 12 else ("strip2" if code < 15 else "strip_o5"))
         for prec in (32, 64):
             ctx = gpu_context([sp], precision=prec, tile=code)
             ctx.step(40)
             f, g = ctx.populations(0)
             ctx.close()
-            if prec not in ref:
-                ref[prec] = (f, g)
+            key = (fam, prec)
+            if key not in ref:
+                ref[key] = (f, g)
             else:
-                assert np.array_equal(f, ref[prec][0]) and np.array_equal(g, ref[prec][1]), (code, prec)
+                assert np.array_equal(f, ref[key][0]) and np.array_equal(g, ref[key][1]), (code, prec)
+            for other_fam in ("tile", "strip", "strip2", "strip_o5"):
+                other = (other_fam, prec)
+                if other_fam == fam or other not in ref:
+                    continue
+                tol = 2e-6 if prec == 32 else 1e-13
+                for a, b in zip((f, g), ref[other]):
+                    assert np.abs(a - b).max() <= tol * np.abs(b).max(), (code, prec, other_fam)
 
 
 def test_initial_state_matches_oracle(orc):

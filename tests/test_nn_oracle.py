@@ -1,0 +1,94 @@
+"""Pins of the surrogate's FP64 oracle (oracle/nn.py) against mathematics:
+adjoint identities, finite differences, exact bf16 rounding of known values,
+and exactness of bilinear resampling on linear fields."""
+import numpy as np
+import pytest
+
+from oracle import nn as O
+
+rng = np.random.default_rng(7)
+
+
+def test_bf16_rounding_known_values():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 3.0e38, 1e-40], np.float32)
+    r = O.bf16_round(x)
+    # 1 + 2^-8 is a tie -> even (1.0); 1 + 3*2^-8 is a tie -> even (1 + 2^-6)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7 and r[3] == 1.0 + 2 ** -6
+    assert r[4] == -2.5
+    assert np.array_equal(O.from_bf16_bits(O.to_bf16_bits(x)), r)
+
+
+def test_conv_adjoints():
+    """<conv(x, w), y> = <x, conv_dx(y, w)> = <w, conv_dw(x, y)> (no bias)."""
+    x = rng.normal(size=(2, 8, 6, 5))
+    w = rng.normal(size=(4, 3, 3, 5))
+    y = rng.normal(size=(2, 8, 6, 4))
+    a = np.sum(O.conv3x3(x, w) * y)
+    assert abs(a - np.sum(x * O.conv3x3_dx(y, w))) < 1e-10 * abs(a)
+    assert abs(a - np.sum(w * O.conv3x3_dw(x, y))) < 1e-10 * abs(a)
+
+
+def test_conv_single_tap_is_shift():
+    """A weight with only the centre tap is a 1x1 channel mix; a corner tap shifts."""
+    x = rng.normal(size=(1, 5, 5, 2))
+    w = np.zeros((1, 3, 3, 2))
+    w[0, 0, 0, 1] = 1.0  # ky = kx = 0 reads x[h-1, w-1]
+    y = O.conv3x3(x, w)
+    assert np.allclose(y[0, 1:, 1:, 0], x[0, :-1, :-1, 1]) and np.all(y[0, 0, :, 0] == 0)
+
+
+def test_pool_upsample_adjoints():
+    x = rng.normal(size=(2, 8, 4, 3))
+    y = rng.normal(size=(2, 4, 2, 3))
+    assert abs(np.sum(O.avgpool2(x) * y) - np.sum(x * O.avgpool2_dx(y))) < 1e-12
+    z = rng.normal(size=(2, 8, 4, 3))
+    assert abs(np.sum(O.upsample2(y) * z) - np.sum(y * O.upsample2_dx(z))) < 1e-12
+
+
+def test_head_gradients_finite_difference():
+    x = rng.normal(size=(2, 4, 4, 3))
+    w = rng.normal(size=3)
+    b = 0.3
+    t = rng.uniform(size=(2, 4, 4))
+    pred, loss, dx, dw, db = O.head(x, w, b, t)
+    eps = 1e-6
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = eps
+        num = (O.head(x, w + e, b, t)[1] - O.head(x, w - e, b, t)[1]) / (2 * eps)
+        assert abs(num - dw[i]) < 1e-7
+    num = (O.head(x, w, b + eps, t)[1] - O.head(x, w, b - eps, t)[1]) / (2 * eps)
+    assert abs(num - db) < 1e-7
+    e = np.zeros_like(x)
+    e[1, 2, 3, 1] = eps
+    num = (O.head(x + e, w, b, t)[1] - O.head(x - e, w, b, t)[1]) / (2 * eps)
+    assert abs(num - dx[1, 2, 3, 1]) < 1e-7
+
+
+def test_adam_first_step_is_sign_step():
+    """With bias correction the first Adam step is lr * g/(|g| + eps)."""
+    p = rng.normal(size=10)
+    g = rng.normal(size=10)
+    p1, m, v = O.adam(p, 0 * p, 0 * p, g, 1e-3, 0.9, 0.999, 1e-8, 1)
+    assert np.allclose(p1, p - 1e-3 * g / (np.abs(g) + 1e-8), atol=1e-12)
+
+
+def test_resample_exact_on_linear_fields():
+    sh, sw = 7, 9
+    yy, xx = np.mgrid[0:sh, 0:sw].astype(float)
+    f = (2.0 * yy / (sh - 1) - 0.5 * xx / (sw - 1) + 0.25)[None]
+    g = O.resample(f, 13, 5)
+    Y, X = np.mgrid[0:13, 0:5].astype(float)
+    assert np.allclose(g[0], 2.0 * Y / 12 - 0.5 * X / 4 + 0.25, atol=1e-12)
+    assert np.array_equal(O.resample(f, sh, sw), f)
+
+
+def test_unet_forward_shapes_and_range():
+    from paper_2311_05091_amd.surrogate import init_params
+    widths = (4, 8)
+    params = init_params(widths=widths, seed=3)
+    x = rng.uniform(size=(1, 16, 16, 32)) * (np.arange(32) < 3)
+    acts = O.unet_forward(params, x, widths)
+    assert acts["e1b"].shape == (1, 8, 8, 8) and acts["last"].shape == (1, 16, 16, 4)
+    pred = O.head(acts["last"], *params["head"])
+    assert pred.shape == (1, 16, 16) and np.all((pred > 0) & (pred < 1))
