@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", default="porous_displacement")
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
+    ap.add_argument("--launch-mode", type=int, default=0,
+                    help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=256,
@@ -103,7 +105,9 @@ def main():
     else:
         ctx.autotune(steps=10)
     code, tx, ty = ctx.tile()
-    print("[bench] tile %d (%dx%d)" % (code, tx, ty), flush=True)
+    if args.launch_mode:
+        ctx.set_launch_mode(args.launch_mode)
+    print("[bench] tile %d (%dx%d), launch mode %d" % (code, tx, ty, args.launch_mode), flush=True)
     ctx.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -131,7 +135,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
         "config": {"workload": wname, "nodes": nodes, "lattice": "D2Q9 x 2 (CH + NS)",
-                   "tile": [tx, ty], "precision": args.precision},
+                   "tile": [tx, ty], "precision": args.precision, "launch_mode": args.launch_mode},
         "roofline": roof,
     }
     ctx.close()

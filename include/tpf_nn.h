@@ -75,9 +75,10 @@ int tpfnn_split(const uint16_t* dy, int32_t Ca, int32_t Cb, int64_t npix, uint16
 int tpfnn_add_inplace(uint16_t* a, const uint16_t* b, int64_t n, void* stream);
 
 /* Output head: z = b + sum_c w[c] x[p,c], pred = sigmoid(z) (FP32).  When target
- * is not NULL also: loss = mean_p (pred - target)^2 (FP64, deterministic),
+ * (values in [0, 1]) is not NULL also the mean binary cross-entropy
+ * loss = mean_p softplus(z) - target z (FP64 sum, deterministic order),
  * dx[p,c] = dz w[c] (bf16), dw[c] = sum_p dz x[p,c], db = sum_p dz (FP32),
- * dz = 2 (pred - target) pred (1 - pred)/npix.  work must hold
+ * dz = (pred - target)/npix.  work must hold
  * tpfnn_head_workspace(npix, C) bytes. */
 size_t tpfnn_head_workspace(int64_t npix, int32_t C);
 int tpfnn_head(const uint16_t* x, int64_t npix, int32_t C, const float* w, const float* b,
@@ -99,9 +100,11 @@ int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* d
                    int32_t dw, void* stream);
 
 /* Network input from physical fields: x[n,h,w,:] = (phi0, (theta - 90 deg)/60 deg,
- * volume scale, 0, ..., 0) padded to 32 channels (bf16). */
-int tpfnn_pack_input(const float* phi0, const float* theta_deg, const float* vol, int32_t N,
-                     int32_t H, int32_t W, uint16_t* x, void* stream);
+ * volume scale, plain initial phi1, 0, ..., 0) padded to 32 channels (bf16).
+ * phi0 and phi1_init are [N,H,W] FP32, theta_deg and vol [N]; phi1_init may be
+ * NULL (channel 3 is then zero). */
+int tpfnn_pack_input(const float* phi0, const float* phi1_init, const float* theta_deg, const float* vol,
+                     int32_t N, int32_t H, int32_t W, uint16_t* x, void* stream);
 
 #ifdef __cplusplus
 }

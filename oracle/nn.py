@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Written from the
 definitions, not for speed: NHWC tensors, 3x3 convolutions with zero
 padding as a sum over the nine taps, their adjoints, 2x2 average pooling,
-nearest upsampling, the sigmoid output head with the mean squared error, Adam,
+nearest upsampling, the sigmoid output head with the binary cross-entropy, Adam,
 bilinear resampling and the encoder-decoder assembled from them.  Shares no
 code with the HIP kernels.
 """
@@ -94,15 +94,16 @@ def upsample2_dx(dy):
 
 
 def head(x, w, b, target=None):
-    """pred = sigmoid(b + x.w); loss = mean (pred - target)^2 and its gradients."""
+    """pred = sigmoid(z), z = b + x.w; with a target in [0, 1] also the mean
+    binary cross-entropy loss = mean(softplus(z) - target z) and its gradients
+    (dz = (pred - target)/npix)."""
     z = x @ w + b
     pred = 1.0 / (1.0 + np.exp(-z))
     if target is None:
         return pred
     npix = pred.size
-    diff = pred - target
-    loss = float(np.mean(diff * diff))
-    dz = 2.0 * diff * pred * (1.0 - pred) / npix
+    loss = float(np.mean(np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z))) - target * z))
+    dz = (pred - target) / npix
     dx = dz[..., None] * w
     dw = (x * dz[..., None]).reshape(-1, x.shape[-1]).sum(0)
     db = float(dz.sum())

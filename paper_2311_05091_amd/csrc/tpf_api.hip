@@ -72,9 +72,15 @@ struct tpf_ctx {
     bool tile_from_user = false;
     bool tuned = false;
     int launch_mode = 0;
+    // persistent launcher state (inside the arena)
+    int* d_ctl = nullptr;        // [2]: next item, failure flag
+    int* d_done = nullptr;       // [ndom]
+    int* d_dom_tiles = nullptr;  // [ndom]
+    int n_cu = 0;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
+    std::vector<int64_t> ev_steps;
     double t_acc_ms = 0;
     int64_t t_launches = 0;
     // current tile table
@@ -281,6 +287,7 @@ static size_t total_bytes(tpf_ctx* c) {
     b += align_up(nd * kRedMaxBlocks * 7 * sizeof(double), 256);
     b += align_up(nd * 4 * sizeof(double), 256);
     b += align_up(18 * max_nodes(c) * sizeof(double), 256);
+    b += align_up(2 * sizeof(int), 256) + 2 * align_up(nd * sizeof(int), 256);
     return b;
 }
 
@@ -416,6 +423,85 @@ static int refresh_live(tpf_ctx* c) {
     return TPF_OK;
 }
 
+// Persistent launch over the current tile table (strip codes 8-10): one
+// kernel runs n steps of every live domain with per-domain step barriers.
+template <typename T, int CH, bool S>
+static int launch_persistent_t(tpf_ctx* c, int ntiles, int n) {
+    int per_cu = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_strip_kernel<T, CH, S>, 64, 0));
+    if (per_cu <= 0) per_cu = 1;
+    const int64_t total = (int64_t)n * ntiles;
+    const int grid = (int)std::min<int64_t>((int64_t)per_cu * c->n_cu, total);
+    hipLaunchKernelGGL((persistent_strip_kernel<T, CH, S>), dim3(grid), dim3(64), 0, c->stream, c->d_doms,
+                       c->d_tiles, ntiles, n, c->d_dom_tiles, c->d_ctl, c->d_done, 1 << 22);
+    HIP_OK(hipGetLastError());
+    return TPF_OK;
+}
+
+template <typename T, bool S>
+static int launch_persistent_shape(tpf_ctx* c, int ntiles, int n) {
+    switch (c->tile_code) {
+        case 8: return launch_persistent_t<T, 16, S>(c, ntiles, n);
+        case 9: return launch_persistent_t<T, 32, S>(c, ntiles, n);
+        case 10: return launch_persistent_t<T, 64, S>(c, ntiles, n);
+    }
+    return TPF_EINVAL;
+}
+
+static bool persistent_ok(const tpf_ctx* c) {
+    return c->launch_mode == 1 && (c->tile_code == 8 || c->tile_code == 9 || c->tile_code == 10);
+}
+
+// n steps of all live domains in persistent launches (chunks fit the
+// 32-bit item counter); returns TPF_EDEVICE if a wait ever timed out.
+static int run_persistent(tpf_ctx* c, int64_t n) {
+    const int ntiles = (int)c->tiles.size();
+    std::vector<int> per(c->doms.size(), 0);
+    for (const int4& t : c->tiles) per[t.x]++;
+    HIP_OK(hipMemcpyAsync(c->d_dom_tiles, per.data(), per.size() * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    const bool S = c->tiles_noS < ntiles;  // some live domain has S: the S-capable instance
+    const int64_t max_chunk = std::max<int64_t>(2, ((int64_t)1 << 30) / std::max(ntiles, 1));
+    int64_t done_steps = 0;
+    while (done_steps < n) {
+        const int64_t m = std::min<int64_t>(n - done_steps, max_chunk);
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_ctl, 2);
+        hipLaunchKernelGGL(zero_ints, dim3((c->doms.size() + 255) / 256), dim3(256), 0, c->stream, c->d_done,
+                           (int)c->doms.size());
+        HIP_OK(hipGetLastError());
+        hipEvent_t a = nullptr, b = nullptr;
+        if (c->timing) {
+            HIP_OK(hipEventCreate(&a));
+            HIP_OK(hipEventCreate(&b));
+            HIP_OK(hipEventRecord(a, c->stream));
+        }
+        int rc = c->precision == 32 ? (S ? launch_persistent_shape<float, true>(c, ntiles, (int)m)
+                                         : launch_persistent_shape<float, false>(c, ntiles, (int)m))
+                                    : (S ? launch_persistent_shape<double, true>(c, ntiles, (int)m)
+                                         : launch_persistent_shape<double, false>(c, ntiles, (int)m));
+        if (rc) return rc;
+        if (c->timing) {
+            HIP_OK(hipEventRecord(b, c->stream));
+            c->ev_pool.push_back(a);
+            c->ev_pool.push_back(b);
+            c->ev_steps.push_back(m);
+        }
+        int ctl[2] = {0, 0};
+        HIP_OK(hipMemcpyAsync(ctl, c->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        if (ctl[1]) return TPF_EDEVICE;
+        for (int di : c->live_list) {
+            auto& h = c->doms[di];
+            h.steps += m;
+            h.dev.parity = (int)((h.dev.parity + m) & 1);
+        }
+        int urc = upload_descriptors(c);
+        if (urc) return urc;
+        done_steps += m;
+    }
+    return TPF_OK;
+}
+
 // Advances the live domains by n steps with one launch per step.  Domains
 // share the step count within the call, so each one's buffer parity is
 // (parity at entry + step index) & 1.
@@ -431,6 +517,7 @@ static int run_steps(tpf_ctx* c, int64_t n) {
         if (c->doms[i].status != TPF_OK) c->doms[i].dev.live = 0;
     rc = upload_descriptors(c);
     if (rc) return rc;
+    if (persistent_ok(c)) return run_persistent(c, n);
     const int ntiles = (int)c->tiles.size();
     const int nnoS = c->tiles_noS;
     for (int64_t s = 0; s < n; ++s) {
@@ -444,6 +531,7 @@ static int run_steps(tpf_ctx* c, int64_t n) {
             HIP_OK(hipEventRecord(b, c->stream));
             c->ev_pool.push_back(a);
             c->ev_pool.push_back(b);
+            c->ev_steps.push_back(1);
         } else {
             HIP_OK(launch_step(c, kModeStep, ntiles, nnoS, off, nullptr));
         }
@@ -614,7 +702,17 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
     c->d_partials = (double*)take(nd * kRedMaxBlocks * 7 * sizeof(double));
     c->d_red = (double*)take(nd * 4 * sizeof(double));
     c->d_scratch = (double*)take(18 * max_nodes(c) * sizeof(double));
+    c->d_ctl = (int*)take(2 * sizeof(int));
+    c->d_done = (int*)take(nd * sizeof(int));
+    c->d_dom_tiles = (int*)take(nd * sizeof(int));
     if (off > need) return TPF_EINVAL;
+    {
+        int dev = 0;
+        HIP_OK(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIP_OK(hipGetDeviceProperties(&prop, dev));
+        c->n_cu = prop.multiProcessorCount;
+    }
     int rc = upload_descriptors(c);
     if (rc) return rc;
     for (size_t i = 0; i < c->doms.size(); ++i) {
@@ -915,7 +1013,7 @@ extern "C" int tpf_autotune(tpf_ctx* c, int32_t steps, double* best_ms) {
 }
 
 extern "C" int tpf_set_launch_mode(tpf_ctx* c, int32_t mode) {
-    if (!c || mode != 0) return TPF_EINVAL;  // the persistent mode is not built yet
+    if (!c || (mode != 0 && mode != 1)) return TPF_EINVAL;
     c->launch_mode = mode;
     return TPF_OK;
 }
@@ -965,10 +1063,11 @@ extern "C" int tpf_kernel_timing(tpf_ctx* c, int32_t enable, double* avg_ms, int
             float ms = 0;
             HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
             acc += ms;
-            ++n;
+            n += c->ev_steps[i / 2];
         }
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);
         c->ev_pool.clear();
+        c->ev_steps.clear();
     }
     if (avg_ms) *avg_ms = n ? acc / n : 0.0;
     if (launches) *launches = n;

@@ -415,15 +415,10 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     }
 }
 
+// One (domain, strip, chunk) tile of the strip kernel at the given step offset.
 template <typename T, int CH, bool HAS_S, int MODE>
-__device__ __forceinline__ void strip_body(const DomDev* __restrict__ doms, const int4* __restrict__ tiles,
-                                           int ntiles, int step_offset, double* __restrict__ mom_out) {
-    __shared__ StripShared<T, HAS_S> sh;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    if (t >= ntiles) return;
-    const int4 tile = tiles[t];
-    const DomDev& d = doms[tile.x];
-    if (!d.live && MODE == kModeStep) return;
+__device__ __forceinline__ void strip_tile(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
+                                           int step_offset, double* __restrict__ mom_out) {
     const KConst<T> K = kconst<T>(d);
     const int cur = (d.parity + step_offset) & 1;
     const bool dS = HAS_S && d.has_s;
@@ -433,12 +428,86 @@ __device__ __forceinline__ void strip_body(const DomDev* __restrict__ doms, cons
     // (the row loaded two iterations earlier)
     constexpr int R = CH + 4;
     for (int r = 0; r < R; r += 3) {
-        strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r, tile.y, tile.z, lane, cur, dS, F0, F1, mom_out);
-        if (r + 1 < R)
-            strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 1, tile.y, tile.z, lane, cur, dS, F1, F2, mom_out);
-        if (r + 2 < R)
-            strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 2, tile.y, tile.z, lane, cur, dS, F2, F0, mom_out);
+        strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r, x0, y0, lane, cur, dS, F0, F1, mom_out);
+        if (r + 1 < R) strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 1, x0, y0, lane, cur, dS, F1, F2, mom_out);
+        if (r + 2 < R) strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 2, x0, y0, lane, cur, dS, F2, F0, mom_out);
     }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE>
+__device__ __forceinline__ void strip_body(const DomDev* __restrict__ doms, const int4* __restrict__ tiles,
+                                           int ntiles, int step_offset, double* __restrict__ mom_out) {
+    __shared__ StripShared<T, HAS_S> sh;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int4 tile = tiles[t];
+    const DomDev& d = doms[tile.x];
+    if (!d.live && MODE == kModeStep) return;
+    strip_tile<T, CH, HAS_S, MODE>(d, sh, tile.y, tile.z, step_offset, mom_out);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent launcher: one launch advances every live domain by nsteps steps.
+// Work items (step s, tile t) are handed out in increasing order of
+// s * ntiles + t from a device counter; before working on step s of a
+// domain, a wavefront waits until all tiles of that domain have finished
+// step s - 1 (per-domain completion counter, release/acquire at device
+// scope).  A wave only ever waits for items handed out before its own, and
+// those are held by running waves, so the queue cannot deadlock; a bounded
+// spin sets a failure flag and lets every wave leave should a wait ever
+// exceed the limit.
+//   ctl[0]: next item, ctl[1]: failure flag; done[dom]: finished items of dom;
+//   dom_tiles[dom]: tiles of dom in the table.
+// All control flow in the loop is uniform across the wave: the counters are
+// updated by every lane with an increment of 1 on lane 0 and 0 elsewhere, and
+// values read from memory are broadcast from lane 0 (readfirstlane).  A
+// "lane 0 only" branch at the end and at the start of the loop lets the
+// compiler thread lanes 1..63 past the fetch into a loop of their own that
+// only lane 0 could end: a hang in a one-wave workgroup, whose barrier
+// enforces no reconvergence.
+// ---------------------------------------------------------------------------
+template <typename T, int CH, bool HAS_S>
+__global__ void __launch_bounds__(64)
+persistent_strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles, int nsteps,
+                        const int* __restrict__ dom_tiles, int* __restrict__ ctl, int* __restrict__ done,
+                        int spin_limit) {
+    __shared__ StripShared<T, HAS_S> sh;
+    const int inc = threadIdx.x == 0 ? 1 : 0;
+    const int total = nsteps * ntiles;
+    for (;;) {
+        const int item = __builtin_amdgcn_readfirstlane(atomicAdd(&ctl[0], inc));
+        if (item >= total) break;
+        const int s = item / ntiles, t = item - s * ntiles;
+        const int4 tile = tiles[t];
+        if (s > 0) {
+            const int need = s * dom_tiles[tile.x];
+            int it = 0;
+            bool fail = false;
+            while (__builtin_amdgcn_readfirstlane(
+                       __hip_atomic_load(&done[tile.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+                if (++it > spin_limit ||
+                    __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
+                    fail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (fail) {
+                __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        const DomDev& d = doms[tile.x];
+        strip_tile<T, CH, HAS_S, kModeStep>(d, sh, tile.y, tile.z, s, nullptr);
+        __syncthreads();
+        __hip_atomic_fetch_add(&done[tile.x], inc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void zero_ints(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 template <typename T, int CH, bool HAS_S, int MODE>

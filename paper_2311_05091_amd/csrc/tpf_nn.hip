@@ -2,7 +2,7 @@
 // 3x3 convolutions on the gfx950 BF16 matrix cores (v_mfma_f32_16x16x32_bf16,
 // FP32 accumulation), their weight and input gradients, and the elementwise
 // pieces of a small encoder-decoder (pooling, upsampling, concatenation,
-// output head with the MSE loss, Adam).
+// output head with the cross-entropy loss, Adam).
 //
 // Matrix-core operand layout (one wavefront, 16x16x32): lane l holds
 //   A: row l%16, k = 8*(l/16) .. 8*(l/16)+7      (8 bf16)
@@ -334,13 +334,16 @@ head_k(const uint16_t* __restrict__ x, int64_t npix, int C, const float* __restr
     const float pr = 1.f / (1.f + __expf(-z));
     if (ok) pred[p] = pr;
     if (!target) return;
-    const float diff = ok ? pr - target[p] : 0.f;
-    const float dz = ok ? 2.f * diff * pr * (1.f - pr) / (float)npix : 0.f;
+    const float tg = ok ? target[p] : 0.f;
+    const float dz = ok ? (pr - tg) / (float)npix : 0.f;
+    // binary cross-entropy with logits: softplus(z) - t z, softplus in the
+    // overflow-free form max(z, 0) + log(1 + exp(-|z|))
+    const float bce = ok ? fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - tg * z : 0.f;
     if (ok)
         for (int c = 0; c < C; ++c) dx[p * C + c] = f2bf(dz * w[c]);
     // C + 2 block sums: dw[0..C), db, loss
     for (int k = 0; k < C + 2; ++k) {
-        double v = k < C ? (double)(dz * xv[k]) : (k == C ? (double)dz : (double)diff * diff);
+        double v = k < C ? (double)(dz * xv[k]) : (k == C ? (double)dz : (double)bce);
         red[threadIdx.x] = v;
         __syncthreads();
         for (int s = kHeadThreads / 2; s > 0; s >>= 1) {
@@ -409,8 +412,9 @@ __global__ void resample_k(const float* __restrict__ src, int N, int sh, int sw,
     dst[i] = v;
 }
 
-__global__ void pack_input_k(const float* __restrict__ phi0, const float* __restrict__ theta,
-                             const float* __restrict__ vol, int N, int HW, uint16_t* __restrict__ x) {
+__global__ void pack_input_k(const float* __restrict__ phi0, const float* __restrict__ phi1,
+                             const float* __restrict__ theta, const float* __restrict__ vol, int N, int HW,
+                             uint16_t* __restrict__ x) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)N * HW) return;
     const int n = (int)(p / HW);
@@ -418,7 +422,8 @@ __global__ void pack_input_k(const float* __restrict__ phi0, const float* __rest
     o[0] = f2bf(phi0[p]);
     o[1] = f2bf((theta[n] - 90.f) / 60.f);
     o[2] = f2bf(vol[n]);
-    for (int c = 3; c < 32; ++c) o[c] = 0;
+    o[3] = phi1 ? f2bf(phi1[p]) : (uint16_t)0;
+    for (int c = 4; c < 32; ++c) o[c] = 0;
 }
 
 inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)((n + t - 1) / t)); }
@@ -629,11 +634,11 @@ extern "C" int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t s
     return launch_status();
 }
 
-extern "C" int tpfnn_pack_input(const float* phi0, const float* theta_deg, const float* vol, int32_t N,
-                                int32_t H, int32_t W, uint16_t* x, void* stream) {
+extern "C" int tpfnn_pack_input(const float* phi0, const float* phi1_init, const float* theta_deg,
+                                const float* vol, int32_t N, int32_t H, int32_t W, uint16_t* x, void* stream) {
     if (!phi0 || !theta_deg || !vol || !x || N <= 0 || H <= 0 || W <= 0) return kEinval;
     const int64_t n = (int64_t)N * H * W;
-    hipLaunchKernelGGL(pack_input_k, grid1(n), dim3(256), 0, (hipStream_t)stream, phi0, theta_deg, vol, N,
-                       H * W, x);
+    hipLaunchKernelGGL(pack_input_k, grid1(n), dim3(256), 0, (hipStream_t)stream, phi0, phi1_init, theta_deg,
+                       vol, N, H * W, x);
     return launch_status();
 }

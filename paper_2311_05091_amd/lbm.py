@@ -242,6 +242,10 @@ class Context:
     def set_tile(self, code: int):
         _check(self.lib.tpf_set_tile(self._h, int(code)), "tpf_set_tile")
 
+    def set_launch_mode(self, mode: int):
+        """0: one launch per step; 1: one persistent launch per call (strip tiles)."""
+        _check(self.lib.tpf_set_launch_mode(self._h, int(mode)), "tpf_set_launch_mode")
+
     def tile(self):
         c, x, y = C.c_int32(), C.c_int32(), C.c_int32()
         _check(self.lib.tpf_get_tile(self._h, C.byref(c), C.byref(x), C.byref(y)), "tpf_get_tile")

@@ -13,7 +13,7 @@ Architecture (4 levels, 32-64-128-256 channels, input 256 x 256):
   decoder level l: up 2x -> conv3x3+ReLU -> concat skip_l -> 2 x conv3x3+ReLU
   head: 1x1 conv -> sigmoid.
 Input channels (padded to 32): phi0, (theta - 90 deg)/60 deg, droplet volume
-(10 x sum(phi1)/area).
+(10 x sum(phi1)/area), and the plain initial phi1 (which places the droplet).
 """
 from __future__ import annotations
 
@@ -28,6 +28,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 NN_LIB_PATH = os.path.join(_PKG, "libtpf_nn.so")
 RES = 256
 IN_CH = 32
+IN_USED = 4
 _nn = None
 
 V = C.c_void_p
@@ -62,7 +63,7 @@ def nnlib() -> C.CDLL:
         "tpfnn_to_bf16": [V, V, I64, V],
         "tpfnn_from_bf16": [V, V, I64, V],
         "tpfnn_resample": [V, I32, I32, I32, V, I32, I32, V],
-        "tpfnn_pack_input": [V, V, V, I32, I32, I32, V, V],
+        "tpfnn_pack_input": [V, V, V, V, I32, I32, I32, V, V],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -109,14 +110,14 @@ def layer_table(widths=(32, 64, 128, 256)) -> List[Tuple[str, int, int]]:
 
 
 def init_params(widths=(32, 64, 128, 256), seed=0) -> Dict[str, Tuple[np.ndarray, np.ndarray]]:
-    """He-normal weights [Cout,3,3,Cin] (input channels beyond the 3 used are zero), zero biases."""
+    """He-normal weights [Cout,3,3,Cin] (input channels beyond the ones used are zero), zero biases."""
     rng = np.random.default_rng(seed)
     params = {}
     for name, cin, cout in layer_table(widths):
-        fan = 9 * (3 if name == "e0a" else cin)
+        fan = 9 * (IN_USED if name == "e0a" else cin)
         w = rng.normal(0.0, math.sqrt(2.0 / fan), (cout, 3, 3, cin))
         if name == "e0a":
-            w[..., 3:] = 0.0
+            w[..., IN_USED:] = 0.0
         params[name] = (w, np.zeros(cout))
     params["head"] = (rng.normal(0.0, math.sqrt(1.0 / widths[0]), widths[0]), np.zeros(1))
     return params
@@ -225,16 +226,21 @@ class UNet:
         _ck(self.lib.tpfnn_conv3x3_fwd(_p(x), N, r, r, cin, _p(self.wb[name]), _p(self.b[name]), cout, 1,
                                        _p(y), self.stream), "conv " + name)
 
-    def pack(self, phi0: np.ndarray, theta_deg: np.ndarray, vol: np.ndarray):
-        """Builds the bf16 network input from [N,256,256] phi0, [N] angles, [N] volumes."""
+    def pack(self, phi0: np.ndarray, theta_deg: np.ndarray, vol: np.ndarray, phi1_init: Optional[np.ndarray] = None):
+        """Builds the bf16 network input from [N,256,256] phi0, [N] angles, [N] volumes
+        and the [N,256,256] plain initial phi1 (zero channel when None)."""
         torch = self.torch
         N = phi0.shape[0]
         self._alloc(N)
         t0 = torch.tensor(np.ascontiguousarray(phi0, np.float32), device=self.dev)
+        t1 = None if phi1_init is None else torch.tensor(np.ascontiguousarray(phi1_init, np.float32),
+                                                          device=self.dev)
         th = torch.tensor(np.asarray(theta_deg, np.float32), device=self.dev)
         vv = torch.tensor(np.asarray(vol, np.float32), device=self.dev)
-        _ck(self.lib.tpfnn_pack_input(_p(t0), _p(th), _p(vv), N, RES, RES, _p(self.act["in"]), self.stream),
-            "pack_input")
+        _ck(self.lib.tpfnn_pack_input(_p(t0), _p(t1) if t1 is not None else None, _p(th), _p(vv), N, RES, RES,
+                                      _p(self.act["in"]), self.stream), "pack_input")
+        # the inputs are read by the kernel queued above: keep them alive until it ran
+        self._pack_keep = (t0, t1, th, vv)
         return N
 
     def forward(self, N):
@@ -331,9 +337,9 @@ class UNet:
         self.adam_step(lr)
         return loss
 
-    def predict(self, phi0, theta_deg, vol) -> np.ndarray:
+    def predict(self, phi0, theta_deg, vol, phi1_init=None) -> np.ndarray:
         """[N,256,256] prediction of phi1 (numpy float32)."""
-        N = self.pack(phi0, theta_deg, vol)
+        N = self.pack(phi0, theta_deg, vol, phi1_init)
         pred = self.forward(N)
         return pred.reshape(N, RES, RES).cpu().numpy()
 

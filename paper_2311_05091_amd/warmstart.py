@@ -65,41 +65,52 @@ def sweep(specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: in
 
 def build_dataset(specs: List[G.DomainSpec], phi_eq: List[np.ndarray], status) -> Dict[str, np.ndarray]:
     """Network inputs/targets on the 256 x 256 grid (GPU bilinear resampling)."""
-    X0, TH, VOL, Y = [], [], [], []
+    X0, X1, TH, VOL, Y = [], [], [], [], []
     for s, phi, st in zip(specs, phi_eq, status):
         if st == TPF_ENAN or not np.isfinite(phi).all():
             continue
-        f0 = S.resample(s.phi0[None], S.RES, S.RES)[0]
-        f1 = S.resample(phi[None], S.RES, S.RES)[0]
-        X0.append(f0)
+        X0.append(S.resample(s.phi0[None], S.RES, S.RES)[0])
+        X1.append(S.resample(s.phi1[None], S.RES, S.RES)[0])
         TH.append(s.theta_deg)
         VOL.append(S.volume_feature(s.phi1))
-        Y.append(np.clip(f1, 0.0, 1.0))
-    return {"phi0": np.array(X0, np.float32), "theta": np.array(TH, np.float32),
-            "vol": np.array(VOL, np.float32), "target": np.array(Y, np.float32)}
+        Y.append(np.clip(S.resample(phi[None], S.RES, S.RES)[0], 0.0, 1.0))
+    return {"phi0": np.array(X0, np.float32), "phi1_init": np.array(X1, np.float32),
+            "theta": np.array(TH, np.float32), "vol": np.array(VOL, np.float32),
+            "target": np.array(Y, np.float32)}
 
 
-def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: float = 1e-3, seed: int = 0,
-          log=print, time_budget_s: float = 1e9) -> S.UNet:
+def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: float = 3e-4, seed: int = 0,
+          log=print, time_budget_s: float = 1e9, warmup_steps: int = 100) -> S.UNet:
+    """Adam on the cross-entropy loss.  The learning rate ramps up linearly over
+    the first ``warmup_steps`` updates (the network has no normalisation
+    layers, and a full-size first step can push the decoder into saturation)
+    and decays along a half cosine to zero at the last planned update."""
     import torch
     net = S.UNet(seed=seed)
     n = len(data["theta"])
     rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     hist = []
+    n_upd = max(epochs * (n // batch), 1)
     for ep in range(epochs):
         perm = rng.permutation(n)
         losses = []
         for b0 in range(0, n - batch + 1, batch):
             idx = perm[b0:b0 + batch]
-            phi0 = data["phi0"][idx]
-            tgt = data["target"][idx]
             flip = rng.random(batch) < 0.5
-            phi0 = np.where(flip[:, None, None], phi0[:, :, ::-1], phi0)
-            tgt = np.where(flip[:, None, None], tgt[:, :, ::-1], tgt)
-            net.pack(np.ascontiguousarray(phi0), data["theta"][idx], data["vol"][idx])
+
+            def mirrored(a):
+                return np.ascontiguousarray(np.where(flip[:, None, None], a[:, :, ::-1], a))
+
+            phi0 = mirrored(data["phi0"][idx])
+            phi1 = mirrored(data["phi1_init"][idx])
+            tgt = mirrored(data["target"][idx])
+            net.pack(phi0, data["theta"][idx], data["vol"][idx], phi1)
             t = torch.tensor(np.ascontiguousarray(tgt).ravel(), device=net.dev)
-            losses.append(net.train_step(batch, t, lr=lr).clone())
+            # linear warm-up, then cosine decay to zero over the planned updates
+            k = net.t + 1
+            step_lr = lr * min(1.0, k / max(warmup_steps, 1)) * 0.5 * (1.0 + math.cos(math.pi * min(k / n_upd, 1.0)))
+            losses.append(net.train_step(batch, t, lr=step_lr).clone())
         ep_loss = float(torch.stack(losses).mean().item()) if losses else float("nan")
         hist.append(ep_loss)
         log(json.dumps({"epoch": ep, "loss": ep_loss, "t": round(time.perf_counter() - t0, 1)}))
@@ -127,18 +138,21 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
     preds = []
     for b0 in range(0, len(specs), B):
         grp = specs[b0:b0 + B]
-        phi0 = np.stack([S.resample(s.phi0[None], S.RES, S.RES)[0] for s in grp])
+        phi0 = S.resample(np.stack([s.phi0 for s in grp]), S.RES, S.RES)
+        phi1 = S.resample(np.stack([s.phi1 for s in grp]), S.RES, S.RES)
         th = np.array([s.theta_deg for s in grp], np.float32)
         vol = np.array([S.volume_feature(s.phi1) for s in grp], np.float32)
-        preds.extend(list(net.predict(phi0, th, vol)))
+        preds.extend(list(net.predict(phi0, th, vol, phi1)))
     fallback = 0
+    fields = []
     for i, s in enumerate(specs):
         try:
             f = S.warm_start_field(preds[i], s.phi0, float(np.sum(s.phi1)))
         except ValueError:
-            f = s.phi1
+            f = None
             fallback += 1
-        ctx.set_phi1(i, f)
+        fields.append(f)
+        ctx.set_phi1(i, s.phi1 if f is None else f)
     _sync()
     t_inf = time.perf_counter() - t0
     rc, steps = ctx.run_to_residual(tol, check_every=check_every, max_steps=max_steps)
@@ -159,8 +173,8 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
     err = []
     for i, s in enumerate(specs):
         pe = plain["phi1"][i]
-        f = S.warm_start_field(preds[i], s.phi0, float(np.sum(s.phi1)))
-        err.append(float(np.linalg.norm(f - pe) / np.linalg.norm(pe)))
+        if fields[i] is not None:
+            err.append(float(np.linalg.norm(fields[i] - pe) / np.linalg.norm(pe)))
     agree = [float(np.linalg.norm(phi_l[i] - plain["phi1"][i]) / np.linalg.norm(plain["phi1"][i]))
              for i in range(len(specs))]
     ps = np.array(plain["steps"], dtype=float)
@@ -171,7 +185,7 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
            "plain_steps_mean": float(ps.mean()), "learned_steps_mean": float(ls.mean()),
            "steps_ratio_mean": float(ps.mean() / max(ls.mean(), 1.0)),
            "plain_capped": int((ps >= max_steps).sum()), "learned_capped": int((ls >= max_steps).sum()),
-           "fallbacks": fallback, "surrogate_rel_l2_mean": float(np.mean(err)),
+           "fallbacks": fallback, "surrogate_rel_l2_mean": float(np.mean(err)) if err else float("nan"),
            "final_state_rel_l2_max": float(np.max(agree))}
     log(json.dumps(out))
     return out
@@ -206,7 +220,7 @@ def main(argv=None):
     ap.add_argument("--eval-cap", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--train-budget-s", type=float, default=240.0)
     ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")
     ap.add_argument("--out", default="gpurun_out/warmstart")

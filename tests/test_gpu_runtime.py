@@ -242,3 +242,28 @@ def test_full_size_porous_workload(orc, prec):
         assert np.abs(g[0] - o[0]).max() <= 2e-6
         for a, b in zip(g[1:], o[1:]):
             assert np.abs(a - b).max() <= 1e-3 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("prec,tile", [(64, 9), (32, 8), (32, 10)])
+def test_persistent_launch_matches_per_step_launch(prec, tile):
+    """One persistent launch per chunk (work queue over (step, tile) with
+    per-domain step barriers) gives the same state as one launch per step."""
+    specs = _mixed_batch() + [G.flat_wall_droplet(nx=200, ny=90, wall_rows=6, R0=20)]
+    _say("persistent", prec, tile)
+    a = gpu_context(specs, precision=prec, tile=tile)
+    a.step(77)
+    b = gpu_context(specs, precision=prec, tile=tile)
+    assert b.lib.tpf_set_launch_mode(b._h, 1) == 0  # noqa: via the raw ABI
+    b.step(77)
+    tol = 1e-13 if prec == 64 else 2e-6
+    for i in range(len(specs)):
+        fa, ga = a.populations(i)
+        fb, gb = b.populations(i)
+        assert b.diag(i)["steps"] == 77
+        assert np.abs(fa - fb).max() <= tol * np.abs(fa).max()
+        assert np.abs(ga - gb).max() <= tol * max(np.abs(ga).max(), 1e-12)
+    # residual-driven runs work in this mode too
+    rc, steps = b.run_to_residual(1e-30, check_every=50, max_steps=100)
+    assert rc == lbm.TPF_EBUDGET and (steps == 100).all()
+    a.close()
+    b.close()

@@ -65,6 +65,21 @@ def test_head_gradients_finite_difference():
     assert abs(num - dx[1, 2, 3, 1]) < 1e-7
 
 
+def test_head_loss_is_cross_entropy():
+    """With x = 0 the logit is the bias: the loss is -t log p - (1 - t) log(1 - p),
+    p = 1/(1 + e^-b), written out in logarithms of probabilities; large logits
+    of the right sign give a vanishing loss."""
+    t = np.array([[[0.0, 0.25], [0.5, 1.0]]])
+    x = np.zeros((1, 2, 2, 3))
+    for b in (-3.0, 0.0, 0.7, 4.0):
+        p = np.exp(b) / (np.exp(b) + 1.0)
+        want = np.mean(-t * np.log(p) - (1 - t) * np.log(1 - p))
+        assert abs(O.head(x, np.ones(3), b, t)[1] - want) < 1e-12
+    tt = np.array([[[0.0, 1.0]]])
+    xx = np.array([[[[-40.0], [40.0]]]])
+    assert O.head(xx, np.ones(1), 0.0, tt)[1] < 1e-16
+
+
 def test_adam_first_step_is_sign_step():
     """With bias correction the first Adam step is lr * g/(|g| + eps)."""
     p = rng.normal(size=10)
