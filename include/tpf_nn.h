@@ -99,6 +99,18 @@ int tpfnn_from_bf16(const uint16_t* x, float* y, int64_t n, void* stream);
 int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* dst, int32_t dh,
                    int32_t dw, void* stream);
 
+/* Mass projection of a predicted phase field (the warm start): phi1_out[i] =
+ * sigmoid(logit(p_i) + c) (1 - phi0_i) with p_i = pred[i] clipped to
+ * [1e-7, 1 - 1e-7] and the shift c in [-40, 40] found by bisection so that
+ * sum(phi1_out) = target; a last factor target/sum (|factor - 1| ~ 1e-7) makes
+ * the sum exact in FP64.  Unlike a multiplicative rescale the field stays in
+ * [0, 1 - phi0], so phi2 = 1 - phi0 - phi1 stays non-negative.  pred, phi0:
+ * [n] FP32 device; phi1_out: [n] FP64 device; info: 2 FP64 device values
+ * (c, sum before the last factor), both NaN (and phi1_out zero) when the
+ * target is out of reach.  One block; deterministic. */
+int tpfnn_mass_project(const float* pred, const float* phi0, int64_t n, double target, double* phi1_out,
+                       double* info, void* stream);
+
 /* Network input from physical fields: x[n,h,w,:] = (phi0, (theta - 90 deg)/60 deg,
  * volume scale, plain initial phi1, 0, ..., 0) padded to 32 channels (bf16).
  * phi0 and phi1_init are [N,H,W] FP32, theta_deg and vol [N]; phi1_init may be

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Written from the
 definitions, not for speed: NHWC tensors, 3x3 convolutions with zero
 padding as a sum over the nine taps, their adjoints, 2x2 average pooling,
 nearest upsampling, the sigmoid output head with the binary cross-entropy, Adam,
-bilinear resampling and the encoder-decoder assembled from them.  Shares no
+bilinear resampling, the mass projection of the warm start and the encoder-decoder assembled from them.  Shares no
 code with the HIP kernels.
 """
 from __future__ import annotations
@@ -133,6 +133,33 @@ def resample(src, dh, dw):
     c = src[:, y1][:, :, x0]
     d = src[:, y1][:, :, x1]
     return (1 - ty) * ((1 - tx) * a + tx * b) + ty * ((1 - tx) * c + tx * d)
+
+
+def mass_project(pred, phi0, target, clip=1e-7):
+    """Warm-start projection: phi1 = sigmoid(logit(p) + c) (1 - phi0), p = pred
+    clipped to [clip, 1 - clip], with the scalar shift c chosen by bisection so
+    that sum(phi1) = target (the sum increases monotonically with c).  Returns
+    (phi1, c)."""
+    p = np.clip(np.asarray(pred, np.float64), clip, 1.0 - clip)
+    z = np.log(p) - np.log1p(-p)
+    w = 1.0 - np.asarray(phi0, np.float64)
+
+    def mass(c):
+        return float(np.sum(w / (1.0 + np.exp(-(z + c)))))
+
+    lo, hi = -40.0, 40.0
+    if not (mass(lo) < target < mass(hi)):
+        raise ValueError("target mass out of reach")
+    for _ in range(200):
+        c = 0.5 * (lo + hi)
+        if c in (lo, hi):
+            break
+        if mass(c) < target:
+            lo = c
+        else:
+            hi = c
+    c = 0.5 * (lo + hi)
+    return w / (1.0 + np.exp(-(z + c))), c
 
 
 # ---------------------------------------------------------------------------

@@ -11,6 +11,8 @@
 // tpfnn_mfma_selftest checks it against a host product.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -412,6 +414,68 @@ __global__ void resample_k(const float* __restrict__ src, int N, int sh, int sw,
     dst[i] = v;
 }
 
+// Mass projection of a predicted phase field by a shift of its logit:
+// phi1 = sigmoid(logit(p) + c) (1 - phi0), with c found by bisection so that
+// sum(phi1) equals the target (the sum is increasing in c).  One block; FP32
+// sigmoid, FP64 sums in a fixed order, so the result is deterministic.
+constexpr int kProjThreads = 1024;
+constexpr float kProjClip = 1e-7f;
+constexpr float kProjRange = 40.f;
+
+__device__ __forceinline__ float proj_logit(float p) {
+    p = fminf(fmaxf(p, kProjClip), 1.f - kProjClip);
+    return logf(p) - log1pf(-p);
+}
+
+__device__ double block_sum_1024(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kProjThreads / 64; ++i) t += red[i];
+    return t;
+}
+
+__global__ void __launch_bounds__(kProjThreads)
+mass_project_k(const float* __restrict__ pred, const float* __restrict__ phi0, int64_t n, double target,
+               double* __restrict__ out, double* __restrict__ info) {
+    __shared__ double red[kProjThreads / 64];
+    auto mass = [&](float c) {
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += kProjThreads) {
+            const float z = proj_logit(pred[i]) + c;
+            acc += (double)((1.f - phi0[i]) / (1.f + __expf(-z)));
+        }
+        return block_sum_1024(acc, red);
+    };
+    const double m_lo = mass(-kProjRange), m_hi = mass(kProjRange);
+    if (!(target > m_lo && target < m_hi)) {
+        for (int64_t i = threadIdx.x; i < n; i += kProjThreads) out[i] = 0.0;
+        if (threadIdx.x == 0) info[0] = info[1] = __builtin_nan("");
+        return;
+    }
+    float lo = -kProjRange, hi = kProjRange;
+    for (int it = 0; it < 48 && lo < hi; ++it) {
+        const float c = 0.5f * (lo + hi);
+        if (c == lo || c == hi) break;
+        if (mass(c) < target) lo = c;
+        else hi = c;
+    }
+    const float c = 0.5f * (lo + hi);
+    const double m = mass(c);
+    const double scale = target / m;  // removes the last bisection residue (|scale - 1| ~ 1e-7)
+    for (int64_t i = threadIdx.x; i < n; i += kProjThreads) {
+        const float z = proj_logit(pred[i]) + c;
+        out[i] = (double)((1.f - phi0[i]) / (1.f + __expf(-z))) * scale;
+    }
+    if (threadIdx.x == 0) {
+        info[0] = c;
+        info[1] = m;
+    }
+}
+
 __global__ void pack_input_k(const float* __restrict__ phi0, const float* __restrict__ phi1,
                              const float* __restrict__ theta, const float* __restrict__ vol, int N, int HW,
                              uint16_t* __restrict__ x) {
@@ -631,6 +695,15 @@ extern "C" int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t s
     if (!src || !dst || N <= 0 || sh <= 0 || sw <= 0 || dh <= 0 || dw <= 0) return kEinval;
     const int64_t n = (int64_t)N * dh * dw;
     hipLaunchKernelGGL(resample_k, grid1(n), dim3(256), 0, (hipStream_t)stream, src, N, sh, sw, dst, dh, dw);
+    return launch_status();
+}
+
+extern "C" int tpfnn_mass_project(const float* pred, const float* phi0, int64_t n, double target,
+                                  double* phi1_out, double* info, void* stream) {
+    if (!pred || !phi0 || !phi1_out || !info || n <= 0 || !(target > 0.0) || !std::isfinite(target))
+        return kEinval;
+    hipLaunchKernelGGL(mass_project_k, dim3(1), dim3(kProjThreads), 0, (hipStream_t)stream, pred, phi0, n, target,
+                       phi1_out, info);
     return launch_status();
 }
 

@@ -64,6 +64,7 @@ def nnlib() -> C.CDLL:
         "tpfnn_from_bf16": [V, V, I64, V],
         "tpfnn_resample": [V, I32, I32, I32, V, I32, I32, V],
         "tpfnn_pack_input": [V, V, V, V, I32, I32, I32, V, V],
+        "tpfnn_mass_project": [V, V, I64, C.c_double, V, V, V],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -82,7 +83,7 @@ EXPORTED_NN = ("tpfnn_mfma_selftest", "tpfnn_conv3x3_fwd", "tpfnn_weight_flip", 
                "tpfnn_conv3x3_wgrad", "tpfnn_relu_bwd", "tpfnn_avgpool2_fwd", "tpfnn_avgpool2_bwd",
                "tpfnn_upsample2_fwd", "tpfnn_upsample2_bwd", "tpfnn_concat", "tpfnn_split",
                "tpfnn_add_inplace", "tpfnn_head_workspace", "tpfnn_head", "tpfnn_adam", "tpfnn_to_bf16",
-               "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input")
+               "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input", "tpfnn_mass_project")
 
 
 def _ck(rc, what):
@@ -364,13 +365,26 @@ def volume_feature(phi1: np.ndarray) -> float:
     return 10.0 * float(np.sum(phi1)) / phi1.size
 
 
-def warm_start_field(pred256: np.ndarray, phi0: np.ndarray, target_mass: float) -> np.ndarray:
-    """Maps a 256 x 256 prediction to a domain: resample to its grid, clip to
-    [0, 1 - phi0] and rescale so that sum(phi1) equals the droplet's mass."""
+def warm_start_field(pred256: np.ndarray, phi0: np.ndarray, target_mass: float, device="cuda:0") -> np.ndarray:
+    """Maps a 256 x 256 prediction to a domain on the GPU: bilinear resampling
+    to its grid, then the mass projection phi1 = sigmoid(logit(p) + c)(1 - phi0)
+    with the shift c that gives sum(phi1) = the droplet's mass.  Raises
+    ValueError when the prediction is not finite or the mass is out of reach."""
+    import torch
+    lib = nnlib()
     ny, nx = phi0.shape
-    f = resample(pred256[None], ny, nx)[0].astype(np.float64)
-    f = np.clip(f, 0.0, 1.0) * (1.0 - phi0)
-    s = f.sum()
-    if not np.isfinite(s) or s <= 0:
-        raise ValueError("empty prediction")
-    return f * (target_mass / s)
+    if not np.isfinite(pred256).all():
+        raise ValueError("non-finite prediction")
+    dev = torch.device(device)
+    st = V(torch.cuda.current_stream(dev).cuda_stream)
+    src = torch.tensor(np.ascontiguousarray(pred256, np.float32), device=dev)
+    p = torch.empty(ny * nx, dtype=torch.float32, device=dev)
+    _ck(lib.tpfnn_resample(_p(src), 1, pred256.shape[0], pred256.shape[1], _p(p), ny, nx, st), "resample")
+    t0 = torch.tensor(np.ascontiguousarray(phi0, np.float32).ravel(), device=dev)
+    out = torch.empty(ny * nx, dtype=torch.float64, device=dev)
+    info = torch.empty(2, dtype=torch.float64, device=dev)
+    _ck(lib.tpfnn_mass_project(_p(p), _p(t0), ny * nx, float(target_mass), _p(out), _p(info), st), "mass_project")
+    c = info.cpu().numpy()
+    if not np.isfinite(c).all():
+        raise ValueError("droplet mass out of reach of the prediction")
+    return out.cpu().numpy().reshape(ny, nx)

@@ -211,6 +211,35 @@ def test_pack_input_channels():
         assert not got[..., 4:].any()
 
 
+def test_mass_project_matches_oracle():
+    """Warm-start projection: the kernel's field follows the FP64 oracle (FP32
+    sigmoid), its sum is the target, and an unreachable target is reported."""
+    _say("mass project")
+    torch = _torch()
+    lib = _lib()
+    ny, nx = 217, 300
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    phi0 = 0.5 - 0.5 * np.tanh((yy - 20.0) / 2.0)
+    pred = np.clip(0.5 + 0.5 * np.tanh((60.0 - np.hypot(xx - 150, yy - 20)) / 3.0)
+                   + 0.05 * rng.normal(size=(ny, nx)), 0.0, 1.0).astype(np.float32)
+    phi0 = phi0.astype(np.float32).astype(np.float64)
+    out = torch.empty(ny * nx, dtype=torch.float64, device="cuda")
+    info = torch.empty(2, dtype=torch.float64, device="cuda")
+    for target in (3000.0, 6000.0, 9000.0):
+        rc = lib.tpfnn_mass_project(_p(_f32_dev(pred.ravel())), _p(_f32_dev(phi0.ravel())), ny * nx, target,
+                                    _p(out), _p(info), None)
+        assert rc == 0
+        ref, c = O.mass_project(pred.astype(np.float64), phi0, target)
+        got = out.cpu().numpy().reshape(ny, nx)
+        ci = info.cpu().numpy()
+        assert abs(ci[0] - c) < 1e-4 * max(1.0, abs(c))
+        assert abs(got.sum() - target) < 1e-10 * target
+        assert np.abs(got - ref).max() < 2e-5
+    rc = lib.tpfnn_mass_project(_p(_f32_dev(pred.ravel())), _p(_f32_dev(phi0.ravel())), ny * nx,
+                                float(ny * nx), _p(out), _p(info), None)
+    assert rc == 0 and np.isnan(info.cpu().numpy()).all()
+
+
 def test_adam_and_resample():
     _say("adam resample")
     torch = _torch()

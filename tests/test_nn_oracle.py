@@ -107,3 +107,21 @@ def test_unet_forward_shapes_and_range():
     assert acts["e1b"].shape == (1, 8, 8, 8) and acts["last"].shape == (1, 16, 16, 4)
     pred = O.head(acts["last"], *params["head"])
     assert pred.shape == (1, 16, 16) and np.all((pred > 0) & (pred < 1))
+
+
+def test_mass_project_recovers_a_known_shift():
+    """A prediction sigmoid(z0) and the mass of sigmoid(z0 + c0)(1 - phi0) as the
+    target: the projection returns c0 and that field; the field stays in
+    [0, 1 - phi0]; a target equal to the unshifted mass gives c = 0."""
+    z0 = rng.normal(size=(20, 30)) * 3.0
+    phi0 = rng.uniform(size=(20, 30)) * (rng.uniform(size=(20, 30)) < 0.3)
+    pred = 1.0 / (1.0 + np.exp(-z0))
+    for c0 in (-2.5, 0.0, 0.7):
+        want = (1.0 - phi0) / (1.0 + np.exp(-(z0 + c0)))
+        f, c = O.mass_project(pred, phi0, want.sum())
+        assert abs(c - c0) < 1e-9
+        assert np.abs(f - want).max() < 1e-9
+        assert abs(f.sum() - want.sum()) < 1e-9 * want.sum()
+        assert np.all(f >= 0) and np.all(f <= 1.0 - phi0 + 1e-15)
+    with pytest.raises(ValueError):
+        O.mass_project(pred, phi0, 2.0 * np.sum(1.0 - phi0))
