@@ -25,10 +25,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 
-# HBM traffic of the fused kernel on this workload, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the factor a plain
-# copy kernel of known size gives; None until measured for the current kernel.
-PMC_TRAFFIC_BYTES = None
+# HBM traffic per launch of the step kernel (strip tiles 64 x 32, FP32) on the
+# porous 4096 x 2048 workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch) scaled by the factor a plain copy kernel of known size
+# gives (1.99975 and 1.0): 429110.2 KiB x 1.99975 + 688128.0 KiB.  Reported
+# only for that kernel, workload and precision; None whenever the kernel
+# source changes after the counters were taken.
+PMC_TRAFFIC_BYTES = {(9, 32, "porous_displacement_4096x2048"): 1.5833e9}
 
 
 def workload(name: str):
@@ -127,7 +130,7 @@ def main():
     achieved = bpn * nodes / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": PMC_TRAFFIC_BYTES,
+            "traffic": None if args.launch_mode else PMC_TRAFFIC_BYTES.get((code, args.precision, wname)),
             "bytes_per_node": bpn, "kernel_ms": round(kern_ms, 5)}
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,

@@ -23,11 +23,40 @@ __device__ __forceinline__ gptr<const T> gpc(const void* p) {
     return (gptr<const T>)p;
 }
 
+// Element at a byte offset from a uniform base: with a 32-bit unsigned offset
+// the compiler uses the scalar-base + vector-offset addressing form, so
+// per-lane addresses cost no 64-bit vector arithmetic.
+// The empty asm statement only re-defines the offset register where it is
+// used (no instruction), so that the zero extension is formed next to the
+// access instead of being hoisted out of the loop, where instruction
+// selection could no longer fold it into the addressing mode.
+template <typename T>
+__device__ __forceinline__ gptr<const T> at_bytes(gptr<const T> base, uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return (gptr<const T>)((__attribute__((address_space(1))) const char*)base + off);
+}
+
+template <typename T>
+__device__ __forceinline__ gptr<T> at_bytes(gptr<T> base, uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return (gptr<T>)((__attribute__((address_space(1))) char*)base + off);
+}
+
+// a / b; in FP32 through the hardware reciprocal (about 1 ulp), in FP64 exact.
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+
 // D2Q9 velocities in the order of the rows of M0 (App. A):
 // 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1) 7 (-1,-1) 8 (1,-1)
 __device__ __constant__ const int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ __constant__ const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ __constant__ const int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// the same tables as compile-time functions (for unrolled address arithmetic)
+constexpr int cx_of(int q) { return q == 1 || q == 5 || q == 8 ? 1 : (q == 3 || q == 6 || q == 7 ? -1 : 0); }
+constexpr int cy_of(int q) { return q == 2 || q == 5 || q == 6 ? 1 : (q == 4 || q == 7 || q == 8 ? -1 : 0); }
+constexpr int opp_of(int q) { return q == 0 ? 0 : (q <= 4 ? (q + 1) % 4 + 1 : (q + 1) % 4 + 5); }
+static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(3) == 1 && opp_of(4) == 2, "opp");
+static_assert(opp_of(5) == 7 && opp_of(6) == 8 && opp_of(7) == 5 && opp_of(8) == 6, "opp");
 
 // Per-domain constants of the step in one precision (derived on the host in
 // FP64, stored once as double and once as float so that kernels read them

@@ -31,9 +31,12 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // Per-node part of the step, shared by the tile and strip kernels: given the
 // stencil values of phi0, phi1, mubar1 (and psi), the pulled populations and
 // the lagged fields of the node, forms the forces, u, p and writes either the
-// post-collision populations and lagged fields or the moments.
+// post-collision populations and lagged fields or the moments.  The node's
+// element index is row + cb / sizeof(T): a uniform part and a per-lane byte
+// offset, so stores use scalar-base addressing.
 template <typename T, int MODE>
-__device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K, bool dS, int id, int N, T ph0, T ph1,
+__device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K, bool dS, int64_t row, uint32_t cb,
+                                            int N, T ph0, T ph1,
                                             T gx0, T gy0, T lap0, T gx1, T gy1, T lap1, T mub,
                                             T gmx, T gmy, T dpsix, T dpsiy, T (&fp)[9], T (&gq)[9],
                                             T lAx, T lAy, T lB, T lCxx, T lCyy, T lCxy, int cur,
@@ -71,7 +74,7 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
     // NS moments; velocity with the solid correction (Sec. 3)
     T mg[9];
     nat_moments(gq, mg);
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = fdiv(T(1), rho);
     const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
     const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
     const T fsx = K.uwx - usx, fsy = K.uwy - usy;
@@ -80,17 +83,18 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
 
     // per-node NS rates from mu/(rho (1 - phi0)) (Sec. 3)
     const T om = T(1) - ph0;
-    const T s2a = om / (muv * inv_rho * K.inv_cfa + T(0.5) * om);
-    const T s2b = om / (muv * inv_rho * K.inv_cfb + T(0.5) * om);
+    const T s2a = fdiv(om, muv * inv_rho * K.inv_cfa + T(0.5) * om);
+    const T s2b = fdiv(om, muv * inv_rho * K.inv_cfb + T(0.5) * om);
 
     // pressure (Sec. 3, 2D constants)
     const T Q = ux * drx + uy * dry;
     const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
-    const T H = K.Kp * (K.AH - (d.bh_zero ? T(0) : K.BH / s2a));
+    const T H = K.Kp * (K.AH - (d.bh_zero ? T(0) : fdiv(K.BH, s2a)));
     const T p = K.pfac * ((mg[0] - gq[0]) + (T(0.5) + H) * Q - K.pw * Bn +
                              T(0.5) * K.Kp * (Bn - lB));
 
     if constexpr (MODE == kModeMoments) {
+        const int64_t id = row + cb / sizeof(T);
         mom_out[id] = double(ph1);
         mom_out[N + id] = double(ux);
         mom_out[2 * N + id] = double(uy);
@@ -124,10 +128,10 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
         T fo[9];
         from_hermite(h, fo, c2);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(fo[q], &fout[q * N + id]);
+        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(fo[q], at_bytes(fout + ((int64_t)q * N + row), cb));
         gptr<T> lagA = gp<T>(d.lagA);
-        lagA[id] = Ax;
-        lagA[N + id] = Ay;
+        *at_bytes(lagA + row, cb) = Ax;
+        *at_bytes(lagA + (N + row), cb) = Ay;
     }
 
     // ---- NS collision in Hermite space ----
@@ -168,14 +172,14 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
         T go[9];
         from_hermite(h, go, c2);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(go[q], &gout[q * N + id]);
-        gp<T>(d.lagB)[id] = Bn;
+        for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(go[q], at_bytes(gout + ((int64_t)q * N + row), cb));
+        *at_bytes(gp<T>(d.lagB) + row, cb) = Bn;
         if (dS) {
             gptr<T> lagC = gp<T>(d.lagC);
-            lagC[id] = Cxx;
-            lagC[N + id] = Cyy;
-            lagC[2 * N + id] = Cxy;
-            gp<T>(d.psi[cur ^ 1])[id] = Sx * uy - Sy * ux;
+            *at_bytes(lagC + row, cb) = Cxx;
+            *at_bytes(lagC + (N + row), cb) = Cyy;
+            *at_bytes(lagC + (2 * (int64_t)N + row), cb) = Cxy;
+            *at_bytes(gp<T>(d.psi[cur ^ 1]) + row, cb) = Sx * uy - Sy * ux;
         }
     }
 }
@@ -271,7 +275,7 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         T fp[9], gq[9];
         pull9(gin, x, y, nx, ny, px, py, N, gq);
         pull9(fin, x, y, nx, ny, px, py, N, fp);
-        node_update<T, MODE>(d, K, dS, id, N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
+        node_update<T, MODE>(d, K, dS, 0, (uint32_t)id * (uint32_t)sizeof(T), N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
                              s_mub[iv], gmx, gmy, dpx, dpy, fp, gq, lagA[id], lagA[N + id], lagB[id],
                              lCxx, lCyy, lCxy, cur, mom_out);
     }
@@ -296,9 +300,41 @@ struct StripShared {
     T psi[HAS_S ? 3 : 1][66];
 };
 
-template <typename T, int CH, bool HAS_S, int MODE>
+// Pulled populations of a node whose source columns x - 1, x, x + 1 are given
+// as byte offsets cb (wrapped periodically once per tile), in row y: the row
+// part of every source address is uniform across the wave (scalar), the
+// column part a per-lane offset.  A source row beyond a wall gives the
+// opposite population of the node itself (half-way bounce-back).
+template <typename T>
+__device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&cb)[3], int y, int nx, int ny,
+                                           int py, int N, T (&out)[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int ys = y - cy_of(q);
+        bool wall = false;
+        if (py) ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+        else wall = ys < 0 || ys >= ny;
+        const int64_t rowq = wall ? (int64_t)opp_of(q) * N + (int64_t)y * nx : (int64_t)q * N + (int64_t)ys * nx;
+        out[q] = *at_bytes(fin + rowq, wall ? cb[1] : cb[1 - cx_of(q)]);
+    }
+}
+
+// Byte offsets of the columns x - 1, x, x + 1 around column x (any integer),
+// wrapped periodically.
+template <typename T>
+__device__ __forceinline__ void wrap_cols(int x, int nx, uint32_t (&cb)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cb[k] = (uint32_t)map_index(x - 1 + k, nx, 1) * (uint32_t)sizeof(T);
+}
+
+// One iteration r of the strip kernel.  PX: the domain is periodic in x, so
+// each lane's source columns are fixed for the whole tile (cb: own column,
+// hb: the halo column of lanes 0..3) and every load uses scalar-base
+// addressing; otherwise the general pull with per-lane wall handling.
+template <typename T, int CH, bool HAS_S, int MODE, bool PX>
 __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, StripShared<T, HAS_S>& sh, int r, int x0,
-                                           int y0, int lane, int cur, bool dS, T (&fL)[9], T (&fU)[9],
+                                           int y0, int lane, int cur, bool dS, const uint32_t (&cb)[3],
+                                           const uint32_t (&hb)[3], T (&fL)[9], T (&fU)[9],
                                            double* __restrict__ mom_out) {
     const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
     const int N = nx * ny;
@@ -308,21 +344,23 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     const int yu = yr - 2;              // row updated in this iteration
     const int x = x0 + lane;
     const bool do_update = (r >= 4) && (yu < ny) && (x < nx);
+    const int64_t rowu = (int64_t)yu * nx;
+    // byte offset of the updated node within its row (x < nx when updating)
+    const uint32_t cu = PX ? cb[1] : (uint32_t)x * (uint32_t)sizeof(T);
 
     // prefetch the NS populations and lagged fields of the row to update
     T gpl[9];
     T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
-    int idu = 0;
     if (do_update) {
-        idu = yu * nx + x;
-        pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gpl);
-        lAx = gpc<T>(d.lagA)[idu];
-        lAy = gpc<T>(d.lagA)[N + idu];
-        lB = gpc<T>(d.lagB)[idu];
+        if constexpr (PX) pull9_cols(gpc<T>(d.g[cur]), cb, yu, nx, ny, py, N, gpl);
+        else pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gpl);
+        lAx = *at_bytes(gpc<T>(d.lagA) + rowu, cu);
+        lAy = *at_bytes(gpc<T>(d.lagA) + (N + rowu), cu);
+        lB = *at_bytes(gpc<T>(d.lagB) + rowu, cu);
         if (dS) {
-            lCxx = gpc<T>(d.lagC)[idu];
-            lCyy = gpc<T>(d.lagC)[N + idu];
-            lCxy = gpc<T>(d.lagC)[2 * N + idu];
+            lCxx = *at_bytes(gpc<T>(d.lagC) + rowu, cu);
+            lCyy = *at_bytes(gpc<T>(d.lagC) + (N + rowu), cu);
+            lCxy = *at_bytes(gpc<T>(d.lagC) + (2 * (int64_t)N + rowu), cu);
         }
     }
 
@@ -330,21 +368,36 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     const int slot5 = r % 5;
     {
         const int sy = map_index(yr, ny, py);
-        const int sx = map_index(x, nx, px);
-        pull9(fin, sx, sy, nx, ny, px, py, N, fL);
+        if constexpr (PX) {
+            pull9_cols(fin, cb, sy, nx, ny, py, N, fL);
+        } else {
+            pull9(fin, map_index(x, nx, px), sy, nx, ny, px, py, N, fL);
+        }
         T s = fL[0];
 #pragma unroll
         for (int q = 1; q < 9; ++q) s += fL[q];
         sh.phi1[slot5][lane + 2] = s;
-        sh.phi0[slot5][lane + 2] = phi0[sy * nx + sx];
+        if constexpr (PX) sh.phi0[slot5][lane + 2] = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
+        else sh.phi0[slot5][lane + 2] = phi0[sy * nx + map_index(x, nx, px)];
         if (lane < 4) {
             const int cx = lane < 2 ? lane : 64 + lane;   // cells 0, 1, 66, 67
-            const int hx = map_index(x0 - 2 + cx, nx, px);
-            T t = pull(fin, 0, hx, sy, nx, ny, px, py, N);
+            T t, t0;
+            if constexpr (PX) {
+                T h[9];
+                pull9_cols(fin, hb, sy, nx, ny, py, N, h);
+                t = h[0];
 #pragma unroll
-            for (int q = 1; q < 9; ++q) t += pull(fin, q, hx, sy, nx, ny, px, py, N);
+                for (int q = 1; q < 9; ++q) t += h[q];
+                t0 = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
+            } else {
+                const int hx = map_index(x0 - 2 + cx, nx, px);
+                t = pull(fin, 0, hx, sy, nx, ny, px, py, N);
+#pragma unroll
+                for (int q = 1; q < 9; ++q) t += pull(fin, q, hx, sy, nx, ny, px, py, N);
+                t0 = phi0[sy * nx + hx];
+            }
             sh.phi1[slot5][cx] = t;
-            sh.phi0[slot5][cx] = phi0[sy * nx + hx];
+            sh.phi0[slot5][cx] = t0;
         }
     }
     __syncthreads();
@@ -410,28 +463,43 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
                 dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
         }
-        node_update<T, MODE>(d, K, dS, idu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
+        node_update<T, MODE>(d, K, dS, rowu, cu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
                              gmy, dpx, dpy, fU, gpl, lAx, lAy, lB, lCxx, lCyy, lCxy, cur, mom_out);
     }
 }
 
 // One (domain, strip, chunk) tile of the strip kernel at the given step offset.
-template <typename T, int CH, bool HAS_S, int MODE>
-__device__ __forceinline__ void strip_tile(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
+template <typename T, int CH, bool HAS_S, int MODE, bool PX>
+__device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
                                            int step_offset, double* __restrict__ mom_out) {
     const KConst<T> K = kconst<T>(d);
     const int cur = (d.parity + step_offset) & 1;
     const bool dS = HAS_S && d.has_s;
     const int lane = threadIdx.x;
+    uint32_t cb[3] = {0, 0, 0}, hb[3] = {0, 0, 0};
+    if constexpr (PX) {
+        wrap_cols<T>(x0 + lane, d.nx, cb);
+        const int cx = lane < 2 ? lane : 64 + lane;   // halo cells 0, 1, 66, 67 (lanes 0..3)
+        wrap_cols<T>(x0 - 2 + cx, d.nx, hb);
+    }
     T F0[9], F1[9], F2[9];
     // row ring: iteration r loads into F[r % 3] and updates with F[(r + 1) % 3]
     // (the row loaded two iterations earlier)
     constexpr int R = CH + 4;
     for (int r = 0; r < R; r += 3) {
-        strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r, x0, y0, lane, cur, dS, F0, F1, mom_out);
-        if (r + 1 < R) strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 1, x0, y0, lane, cur, dS, F1, F2, mom_out);
-        if (r + 2 < R) strip_iter<T, CH, HAS_S, MODE>(d, K, sh, r + 2, x0, y0, lane, cur, dS, F2, F0, mom_out);
+        strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r, x0, y0, lane, cur, dS, cb, hb, F0, F1, mom_out);
+        if (r + 1 < R)
+            strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r + 1, x0, y0, lane, cur, dS, cb, hb, F1, F2, mom_out);
+        if (r + 2 < R)
+            strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r + 2, x0, y0, lane, cur, dS, cb, hb, F2, F0, mom_out);
     }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE>
+__device__ __forceinline__ void strip_tile(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
+                                           int step_offset, double* __restrict__ mom_out) {
+    if (d.px) strip_rows<T, CH, HAS_S, MODE, true>(d, sh, x0, y0, step_offset, mom_out);
+    else strip_rows<T, CH, HAS_S, MODE, false>(d, sh, x0, y0, step_offset, mom_out);
 }
 
 template <typename T, int CH, bool HAS_S, int MODE>
@@ -664,7 +732,7 @@ __device__ __forceinline__ void strip2_iter(const DomDev& d, const KConst<T>& K,
                 dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
         }
-        node_update<T, MODE>(d, K, dS, yu * nx + x, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
+        node_update<T, MODE>(d, K, dS, (int64_t)yu * nx, (uint32_t)x * (uint32_t)sizeof(T), N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
                              gmx, gmy, dpx, dpy, fU, gU.g, gU.lAx, gU.lAy, gU.lB, gU.lCxx, gU.lCyy, gU.lCxy,
                              cur, mom_out);
     }

@@ -101,6 +101,41 @@ def build_dataset(specs: List[G.DomainSpec], phi_eq: List[np.ndarray], status) -
             "target": np.array(Y, np.float32)}
 
 
+def predict_fields(net: S.UNet, specs: List[G.DomainSpec], batch: int = 32):
+    """Warm-start fields (mass-projected, on each domain's grid) for the
+    domains; None where the prediction is unusable."""
+    preds = []
+    for b0 in range(0, len(specs), batch):
+        grp = specs[b0:b0 + batch]
+        phi0 = np.stack([S.resample(sp.phi0[None], S.RES, S.RES)[0] for sp in grp])
+        phi1 = np.stack([S.resample(sp.phi1[None], S.RES, S.RES)[0] for sp in grp])
+        th = np.array([sp.theta_deg for sp in grp], np.float32)
+        vol = np.array([S.volume_feature(sp.phi1) for sp in grp], np.float32)
+        preds.extend(list(net.predict(phi0, th, vol, phi1)))
+    fields = []
+    for sp, pr in zip(specs, preds):
+        try:
+            fields.append(S.warm_start_field(pr, sp.phi0, float(np.sum(sp.phi1))))
+        except ValueError:
+            fields.append(None)
+    return fields
+
+
+def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def calibrate_gate(net: S.UNet, specs: List[G.DomainSpec], phi_eq: List[np.ndarray], q: float = 0.75) -> float:
+    """Gate of the warm start from validation domains (not trained on): the
+    q-quantile of the surrogate's error (rel. L2 of the warm-start field
+    against the swept equilibrium).  A prediction that lies closer than this
+    to the plain initial condition carries no information beyond it, and the
+    plain start is kept."""
+    fields = predict_fields(net, specs)
+    errs = [rel_l2(f, e) for f, e in zip(fields, phi_eq) if f is not None and np.isfinite(e).all()]
+    return float(np.quantile(errs, q)) if errs else 0.0
+
+
 def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: float = 3e-4, seed: int = 0,
           log=print, time_budget_s: float = 1e9, warmup_steps: int = 100) -> S.UNet:
     """Adam on the cross-entropy loss.  The learning rate ramps up linearly over
@@ -143,14 +178,15 @@ def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: flo
 
 
 def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int,
-             precision: int = 32, launch_mode: int = 0, log=print) -> Dict:
+             precision: int = 32, launch_mode: int = 0, gate: float = 0.0, log=print) -> Dict:
     """Plain vs learned time to r < tol on the same held-out domains, each side
     one batch (converged domains retire).
 
-    Learned side, timed as a whole: inference, mass-projected warm start and
-    relaxation to the tolerance; a domain that turns non-finite restarts from
-    the plain initial condition afterwards (its wasted steps count against
-    it).  Work is compared as node-steps (each domain's steps x its nodes),
+    Learned side, timed as a whole: inference, mass-projected warm start
+    (kept only where it differs from the plain initial condition by at least
+    ``gate`` in relative L2) and relaxation to the tolerance; a domain that
+    turns non-finite restarts from the plain initial condition afterwards (its
+    wasted steps count against it).  Work is compared as node-steps (each domain's steps x its nodes),
     which is what the batched GPU time follows once the batch is large; the
     batch wall times are reported beside it."""
     plain = sweep(specs, tol, check_every, max_steps, precision=precision, launch_mode=launch_mode)
@@ -164,24 +200,14 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
         ctx.set_launch_mode(launch_mode)
     _sync()
     t0 = time.perf_counter()
-    B = 32
-    preds = []
-    for b0 in range(0, len(specs), B):
-        grp = specs[b0:b0 + B]
-        phi0 = S.resample(np.stack([sp.phi0 for sp in grp]), S.RES, S.RES)
-        phi1 = S.resample(np.stack([sp.phi1 for sp in grp]), S.RES, S.RES)
-        th = np.array([sp.theta_deg for sp in grp], np.float32)
-        vol = np.array([S.volume_feature(sp.phi1) for sp in grp], np.float32)
-        preds.extend(list(net.predict(phi0, th, vol, phi1)))
-    fields = []
-    empty = 0
+    fields = predict_fields(net, specs)
+    empty = sum(f is None for f in fields)
+    gated = 0
     for i, sp in enumerate(specs):
-        try:
-            f = S.warm_start_field(preds[i], sp.phi0, float(np.sum(sp.phi1)))
-        except ValueError:
+        f = fields[i]
+        if f is not None and rel_l2(f, sp.phi1) < gate:
             f = None
-            empty += 1
-        fields.append(f)
+            gated += 1
         ctx.set_phi1(i, sp.phi1 if f is None else f)
     _sync()
     t_inf = time.perf_counter() - t0
@@ -222,7 +248,7 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
            "steps_ratio_median": float(np.median(ratio)) if ratio.size else float("nan"),
            "faster_share": float(np.mean(ratio > 1.0)) if ratio.size else float("nan"),
            "plain_capped": int((ps >= max_steps).sum()), "learned_capped": int((ls >= max_steps).sum()),
-           "empty_predictions": empty, "restarted": len(bad),
+           "empty_predictions": empty, "gate": gate, "gated_to_plain": gated, "restarted": len(bad),
            "plain_nan": int(np.sum(np.asarray(plain["status"]) == TPF_ENAN)),
            "learned_nan": int(np.sum(np.asarray(status_l) == TPF_ENAN)),
            "surrogate_rel_l2_mean": float(np.mean(finite_err)) if finite_err else float("nan"),
@@ -235,9 +261,9 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
     return out
 
 
-def save_params(net: S.UNet, path: str):
+def save_params(net: S.UNet, path: str, gate: float = 0.0):
     p = net.params_numpy()
-    flat = {}
+    flat = {"gate": np.array(gate)}
     for k, (w, b) in p.items():
         flat[k + ".w"] = w.astype(np.float32)
         flat[k + ".b"] = b.astype(np.float32)
@@ -245,9 +271,11 @@ def save_params(net: S.UNet, path: str):
 
 
 def load_params(path: str):
+    """(params, gate) from a file written by save_params."""
     z = np.load(path)
-    names = sorted({k.rsplit(".", 1)[0] for k in z.files})
-    return {k: (z[k + ".w"].astype(np.float64), z[k + ".b"].astype(np.float64)) for k in names}
+    names = sorted({k.rsplit(".", 1)[0] for k in z.files if "." in k})
+    gate = float(z["gate"]) if "gate" in z.files else 0.0
+    return {k: (z[k + ".w"].astype(np.float64), z[k + ".b"].astype(np.float64)) for k in names}, gate
 
 
 def main(argv=None):
@@ -268,6 +296,8 @@ def main(argv=None):
     ap.add_argument("--train-budget-s", type=float, default=240.0)
     ap.add_argument("--sweep-group", type=int, default=64, help="domains per sweep context (logged per group)")
     ap.add_argument("--launch-mode", type=int, default=0, help="0: one launch per step; 1: persistent")
+    ap.add_argument("--gate", type=float, default=-1.0,
+                    help="warm-start gate (rel. L2 to the plain start); < 0: calibrated on validation domains")
     ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")
     ap.add_argument("--out", default="gpurun_out/warmstart")
     args = ap.parse_args(argv)
@@ -281,7 +311,10 @@ def main(argv=None):
 
     result = {"config": vars(args)}
     if args.weights:
-        net = S.UNet(params=load_params(args.weights))
+        params, gate = load_params(args.weights)
+        net = S.UNet(params=params)
+        if args.gate >= 0:
+            gate = args.gate
     else:
         specs = G.batched_sweep(n_domains=args.train_domains, smin=args.smin, smax=args.smax)
         log(json.dumps({"phase": "sweep", "domains": len(specs), "nodes": sum(s.nx * s.ny for s in specs)}))
@@ -292,7 +325,10 @@ def main(argv=None):
                            "converged": conv, "nan": int(np.sum(sw["status"] == TPF_ENAN)),
                            "steps_mean": float(np.mean(sw["steps"]))}
         log(json.dumps({"phase": "sweep_done", **result["sweep"]}))
-        data = build_dataset(specs, sw["phi1"], sw["status"])
+        # the last tenth of the domains is validation (calibrates the gate), not trained on
+        n_val = max(1, len(specs) // 10)
+        val_specs, val_eq = specs[-n_val:], sw["phi1"][-n_val:]
+        data = build_dataset(specs[:-n_val], sw["phi1"][:-n_val], sw["status"][:-n_val])
         del sw
         log(json.dumps({"phase": "train", "samples": int(len(data["theta"]))}))
         net = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
@@ -300,12 +336,15 @@ def main(argv=None):
         result["train"] = {"samples": int(len(data["theta"])), "loss_first": net.history[0],
                            "loss_last": net.history[-1], "epochs": len(net.history),
                            "params": net.n_params(), "gflop_fwd_per_sample": net.flops_per_sample() / 1e9}
-        save_params(net, os.path.join(args.out, "unet_weights.npz"))
+        gate = calibrate_gate(net, val_specs, val_eq) if args.gate < 0 else args.gate
+        result["train"]["gate"] = gate
+        result["train"]["validation_domains"] = n_val
+        save_params(net, os.path.join(args.out, "unet_weights.npz"), gate)
         log(json.dumps({"phase": "train_done", **result["train"]}))
     held = G.held_out_set(n_domains=args.eval_domains, s=256)
     log(json.dumps({"phase": "evaluate", "domains": len(held)}))
     result["evaluate"] = evaluate(net, held, args.tol, args.check_every, args.eval_cap,
-                                  launch_mode=args.launch_mode, log=log)
+                                  launch_mode=args.launch_mode, gate=gate, log=log)
     with open(os.path.join(args.out, "result.json"), "w") as f:
         json.dump(result, f, indent=1, default=float)
     ev = result["evaluate"]
