@@ -142,8 +142,13 @@ int tpf_tile_codes(int32_t* n, int32_t* codes, int32_t* tx, int32_t* ty);
 int tpf_autotune(tpf_ctx* ctx, int32_t steps, double* best_ms);
 
 /* Launch mode of tpf_step / tpf_run_to_residual: 0 = one kernel launch per
- * step over all live domains' tiles; 1 = persistent launch that advances
- * all live domains through a chunk of steps with per-domain step barriers. */
+ * step over all live domains' tiles; 1 = one persistent launch per call that
+ * advances all live domains through the steps: a work queue of (step, tile)
+ * items with a per-domain barrier between steps (device-scope counters).
+ * Mode 1 applies to the strip tile codes 8-10; with any other tile code the
+ * calls fall back to one launch per step.  Both modes give the same state.
+ * A barrier wait that exceeds its spin bound (it cannot in a correct run)
+ * makes the call return TPF_EDEVICE.  TPF_EINVAL for other modes. */
 int tpf_set_launch_mode(tpf_ctx* ctx, int32_t mode);
 
 /* Bytes a step moves by definition per node: 18 population reads and writes,
