@@ -47,7 +47,8 @@ int tpfnn_weight_flip(const uint16_t* w, int32_t Cout, int32_t Cin, uint16_t* wt
 /* dw[co,ky,kx,ci] = sum_{n,h,w} dy[n,h,w,co] x[n,h+ky-1,w+kx-1,ci] and, when db is
  * not NULL, db[co] = sum dy[...,co]; both FP32, overwritten.  work must hold
  * tpfnn_wgrad_workspace(...) bytes (split-K partial sums, reduced in a fixed
- * order so that the result is deterministic). */
+ * order so that the result is deterministic).  Cin, Cout multiples of 32,
+ * H*W a multiple of 64; with db, Cout must divide 256 (TPF_EINVAL otherwise). */
 size_t tpfnn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout);
 int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_t N, int32_t H, int32_t W,
                         int32_t Cin, int32_t Cout, float* dw, float* db, void* work,

@@ -211,14 +211,37 @@ __global__ void sum_splits_k(const float* __restrict__ part, int splits, int64_t
     out[i] = s;
 }
 
-// db partials: block b sums pixels [b*chunk, (b+1)*chunk) for every channel.
-__global__ void bias_grad_part_k(const uint16_t* __restrict__ dy, int P, int C, int chunk,
-                                 float* __restrict__ part) {
-    const int pbeg = blockIdx.x * chunk, pend = min(P, pbeg + chunk);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float s = 0.f;
-        for (int p = pbeg; p < pend; ++p) s += bf2f(dy[(size_t)p * C + c]);
-        part[(size_t)blockIdx.x * C + c] = s;
+// db partials: block b sums pixels [b*kBiasPix, (b+1)*kBiasPix) for every
+// channel.  A thread reads 8 consecutive channels (16 bytes) of every
+// G-th pixel, G = 256/(C/8), so a wave reads whole pixel rows (coalesced);
+// the G partial sums of a channel are then added in a fixed order.
+// C is a multiple of 8 that divides 256.
+constexpr int kBiasPix = 1024;
+
+__global__ void __launch_bounds__(256)
+bias_grad_part_k(const uint16_t* __restrict__ dy, int P, int C, float* __restrict__ part) {
+    __shared__ float red[256][8];
+    const int tpp = C / 8, G = 256 / tpp;
+    const int c8 = threadIdx.x % tpp, pl = threadIdx.x / tpp;
+    const int pbeg = blockIdx.x * kBiasPix, pend = min(P, pbeg + kBiasPix);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int p = pbeg + pl; p < pend; p += G) {
+        const uint4 v = *(const uint4*)(dy + (size_t)p * C + 8 * c8);
+        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s[2 * j] += bf2f((uint16_t)(u[j] & 0xffffu));
+            s[2 * j + 1] += bf2f((uint16_t)(u[j] >> 16));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[threadIdx.x][j] = s[j];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        const int cc = threadIdx.x / 8, j = threadIdx.x % 8;
+        float t = 0.f;
+        for (int g = 0; g < G; ++g) t += red[g * tpp + cc][j];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -324,7 +347,7 @@ __global__ void __launch_bounds__(kHeadThreads)
 head_k(const uint16_t* __restrict__ x, int64_t npix, int C, const float* __restrict__ w,
        const float* __restrict__ b, float* __restrict__ pred, const float* __restrict__ target,
        uint16_t* __restrict__ dx, double* __restrict__ part) {
-    __shared__ double red[kHeadThreads];
+    __shared__ double red[kHeadThreads / 64][34];
     const int64_t p = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x;
     const bool ok = p < npix;
     float xv[32];
@@ -343,29 +366,41 @@ head_k(const uint16_t* __restrict__ x, int64_t npix, int C, const float* __restr
     const float bce = ok ? fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - tg * z : 0.f;
     if (ok)
         for (int c = 0; c < C; ++c) dx[p * C + c] = f2bf(dz * w[c]);
-    // C + 2 block sums: dw[0..C), db, loss
+    // C + 2 block sums (dw[0..C), db, loss): a shuffle tree per wave, then the
+    // four wave sums in order (fixed order throughout, so deterministic)
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     for (int k = 0; k < C + 2; ++k) {
         double v = k < C ? (double)(dz * xv[k]) : (k == C ? (double)dz : (double)bce);
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = kHeadThreads / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 2) + k] = red[0];
-        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (ln == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < C + 2) {
+        double t = 0.0;
+        for (int i = 0; i < kHeadThreads / 64; ++i) t += red[i][threadIdx.x];
+        part[(size_t)blockIdx.x * (C + 2) + threadIdx.x] = t;
     }
 }
 
-__global__ void head_final_k(const double* __restrict__ part, int nblk, int C, int64_t npix,
-                             float* __restrict__ dw, float* __restrict__ db, double* __restrict__ loss) {
-    const int k = threadIdx.x;
-    if (k >= C + 2) return;
+// One block per output k: strided partial sums per thread, then a tree.
+__global__ void __launch_bounds__(256)
+head_final_k(const double* __restrict__ part, int nblk, int C, int64_t npix, float* __restrict__ dw,
+             float* __restrict__ db, double* __restrict__ loss) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
     double s = 0.0;
-    for (int i = 0; i < nblk; ++i) s += part[(size_t)i * (C + 2) + k];
-    if (k < C) dw[k] = (float)s;
-    else if (k == C) db[0] = (float)s;
-    else loss[0] = s / (double)npix;
+    for (int i = threadIdx.x; i < nblk; i += 256) s += part[(size_t)i * (C + 2) + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (k < C) dw[k] = (float)red[0];
+        else if (k == C) db[0] = (float)red[0];
+        else loss[0] = red[0] / (double)npix;
+    }
 }
 
 __global__ void adam_k(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
@@ -542,7 +577,7 @@ extern "C" size_t tpfnn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t
     const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
     const int nb = (int)((P + chunk - 1) / chunk);
     const size_t wpart = (size_t)nb * Cout * 9 * Cin * sizeof(float);
-    const size_t bpart = (size_t)nb * Cout * sizeof(float);
+    const size_t bpart = (size_t)((P + kBiasPix - 1) / kBiasPix) * Cout * sizeof(float);
     return wpart + bpart + 256;
 }
 
@@ -552,6 +587,7 @@ extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_
     if (!x || !dy || !dw || !work || N <= 0 || H <= 0 || W <= 0) return kEinval;
     if (Cin % 32 || Cout % 32 || ((int64_t)H * W) % 64) return kEinval;
     if (work_bytes < tpfnn_wgrad_workspace(N, H, W, Cin, Cout)) return kEinval;
+    if (db && 256 % Cout) return kEinval;
     const int64_t P = (int64_t)N * H * W;
     if (P > 0x7fffffff) return kEinval;
     const int S = wgrad_splits(P);
@@ -575,9 +611,10 @@ extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_
     hipLaunchKernelGGL(sum_splits_k, grid1(nw), dim3(256), 0, st, wpart, nb, nw, dw);
     if (hipGetLastError() != hipSuccess) return kEdevice;
     if (db) {
-        hipLaunchKernelGGL(bias_grad_part_k, dim3(nb), dim3(256), 0, st, dy, (int)P, Cout, chunk, bpart);
+        const int nbb = (int)((P + kBiasPix - 1) / kBiasPix);
+        hipLaunchKernelGGL(bias_grad_part_k, dim3(nbb), dim3(256), 0, st, dy, (int)P, Cout, bpart);
         if (hipGetLastError() != hipSuccess) return kEdevice;
-        hipLaunchKernelGGL(sum_splits_k, grid1(Cout), dim3(256), 0, st, bpart, nb, (int64_t)Cout, db);
+        hipLaunchKernelGGL(sum_splits_k, grid1(Cout), dim3(256), 0, st, bpart, nbb, (int64_t)Cout, db);
     }
     return launch_status();
 }
@@ -662,7 +699,7 @@ extern "C" int tpfnn_head(const uint16_t* x, int64_t npix, int32_t C, const floa
                        dx, (double*)work);
     if (hipGetLastError() != hipSuccess) return kEdevice;
     if (target)
-        hipLaunchKernelGGL(head_final_k, dim3(1), dim3(64), 0, st, (const double*)work, (int)nblk, C, npix, dw,
+        hipLaunchKernelGGL(head_final_k, dim3(C + 2), dim3(256), 0, st, (const double*)work, (int)nblk, C, npix, dw,
                            db, loss);
     return launch_status();
 }

@@ -388,3 +388,49 @@ def warm_start_field(pred256: np.ndarray, phi0: np.ndarray, target_mass: float, 
     if not np.isfinite(c).all():
         raise ValueError("droplet mass out of reach of the prediction")
     return out.cpu().numpy().reshape(ny, nx)
+
+
+def main(argv=None):
+    """Times forward passes and training steps of the network on synthetic
+    inputs (smooth random fields): ms per step and effective TFLOP/s, with
+    3 x the forward multiply-adds counted per training sample."""
+    import argparse
+    import json
+    import time
+    import torch
+    ap = argparse.ArgumentParser(description="surrogate throughput on synthetic inputs")
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    args = ap.parse_args(argv)
+    rng = np.random.default_rng(0)
+    N = args.batch
+    yy, xx = np.mgrid[0:RES, 0:RES]
+    phi0 = np.stack([0.5 - 0.5 * np.tanh((yy - 24 - 8 * np.sin(2 * np.pi * xx / RES + rng.uniform(0, 6))) / 2.0)
+                     for _ in range(N)])
+    phi1 = np.stack([(1 - phi0[i]) * (0.5 + 0.5 * np.tanh((50 - np.hypot(xx - 128, yy - 30)) / 2.0))
+                     for i in range(N)])
+    net = UNet(seed=0)
+    net.pack(phi0, rng.uniform(30, 150, N), np.full(N, 0.6), phi1)
+    tgt = torch.tensor(phi1.astype(np.float32).ravel(), device=net.dev)
+    for _ in range(args.warmup):
+        net.train_step(N, tgt, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(N, tgt, lr=1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(N)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / args.steps
+    f = net.flops_per_sample()
+    print(json.dumps({"batch": N, "train_ms": round(t_train * 1e3, 3), "forward_ms": round(t_fwd * 1e3, 3),
+                      "train_tflops": round(3 * f * N / t_train / 1e12, 2),
+                      "forward_tflops": round(f * N / t_fwd / 1e12, 2)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
