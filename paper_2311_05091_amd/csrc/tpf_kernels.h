@@ -308,14 +308,27 @@ struct StripShared {
 template <typename T>
 __device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&cb)[3], int y, int nx, int ny,
                                            int py, int N, T (&out)[9]) {
+    int ym = y - 1, yp = y + 1;
+    bool wall = false;
+    if (py) {
+        ym = ym < 0 ? ym + ny : ym;
+        yp = yp >= ny ? yp - ny : yp;
+    } else {
+        wall = ym < 0 || yp >= ny;
+    }
+    if (!wall) {
+        // source row of population q is y - cy_q: rows[1 - cy_q]
+        gptr<const T> rows[3] = {fin + (int64_t)ym * nx, fin + (int64_t)y * nx, fin + (int64_t)yp * nx};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) out[q] = *at_bytes(rows[1 - cy_of(q)] + (int64_t)q * N, cb[1 - cx_of(q)]);
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        int ys = y - cy_of(q);
-        bool wall = false;
-        if (py) ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-        else wall = ys < 0 || ys >= ny;
-        const int64_t rowq = wall ? (int64_t)opp_of(q) * N + (int64_t)y * nx : (int64_t)q * N + (int64_t)ys * nx;
-        out[q] = *at_bytes(fin + rowq, wall ? cb[1] : cb[1 - cx_of(q)]);
+        const int ys = y - cy_of(q);
+        const bool w = ys < 0 || ys >= ny;
+        const int64_t rowq = w ? (int64_t)opp_of(q) * N + (int64_t)y * nx : (int64_t)q * N + (int64_t)ys * nx;
+        out[q] = *at_bytes(fin + rowq, w ? cb[1] : cb[1 - cx_of(q)]);
     }
 }
 
@@ -348,7 +361,33 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     // byte offset of the updated node within its row (x < nx when updating)
     const uint32_t cu = PX ? cb[1] : (uint32_t)x * (uint32_t)sizeof(T);
 
+    // A. loads of row yr: the pulled CH populations and phi0 of the own
+    // column and (lanes 0..3) of the 4 halo columns; issued before the NS
+    // prefetch below, so that waiting for them does not wait for that too
+    const int slot5 = r % 5;
+    const int sy = map_index(yr, ny, py);
+    const int cxh = lane < 2 ? lane : 64 + lane;   // halo cells 0, 1, 66, 67 (lanes 0..3)
+    T hF[9], p0v, h0v = T(0);
+    if constexpr (PX) {
+        pull9_cols(fin, cb, sy, nx, ny, py, N, fL);
+        p0v = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
+        if (lane < 4) {
+            pull9_cols(fin, hb, sy, nx, ny, py, N, hF);
+            h0v = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
+        }
+    } else {
+        const int sx = map_index(x, nx, px);
+        pull9(fin, sx, sy, nx, ny, px, py, N, fL);
+        p0v = phi0[sy * nx + sx];
+        if (lane < 4) {
+            const int hx = map_index(x0 - 2 + cxh, nx, px);
+            pull9(fin, hx, sy, nx, ny, px, py, N, hF);
+            h0v = phi0[sy * nx + hx];
+        }
+    }
+
     // prefetch the NS populations and lagged fields of the row to update
+    // (used in C)
     T gpl[9];
     T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
     if (do_update) {
@@ -364,40 +403,19 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
         }
     }
 
-    // A. phi0, phi1 of row yr (own column + lanes 0..3 for the 4 halo columns)
-    const int slot5 = r % 5;
+    // phi1 = sum of the pulled populations, into the LDS ring with phi0
     {
-        const int sy = map_index(yr, ny, py);
-        if constexpr (PX) {
-            pull9_cols(fin, cb, sy, nx, ny, py, N, fL);
-        } else {
-            pull9(fin, map_index(x, nx, px), sy, nx, ny, px, py, N, fL);
-        }
         T s = fL[0];
 #pragma unroll
         for (int q = 1; q < 9; ++q) s += fL[q];
         sh.phi1[slot5][lane + 2] = s;
-        if constexpr (PX) sh.phi0[slot5][lane + 2] = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
-        else sh.phi0[slot5][lane + 2] = phi0[sy * nx + map_index(x, nx, px)];
+        sh.phi0[slot5][lane + 2] = p0v;
         if (lane < 4) {
-            const int cx = lane < 2 ? lane : 64 + lane;   // cells 0, 1, 66, 67
-            T t, t0;
-            if constexpr (PX) {
-                T h[9];
-                pull9_cols(fin, hb, sy, nx, ny, py, N, h);
-                t = h[0];
+            T t = hF[0];
 #pragma unroll
-                for (int q = 1; q < 9; ++q) t += h[q];
-                t0 = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
-            } else {
-                const int hx = map_index(x0 - 2 + cx, nx, px);
-                t = pull(fin, 0, hx, sy, nx, ny, px, py, N);
-#pragma unroll
-                for (int q = 1; q < 9; ++q) t += pull(fin, q, hx, sy, nx, ny, px, py, N);
-                t0 = phi0[sy * nx + hx];
-            }
-            sh.phi1[slot5][cx] = t;
-            sh.phi0[slot5][cx] = t0;
+            for (int q = 1; q < 9; ++q) t += hF[q];
+            sh.phi1[slot5][cxh] = t;
+            sh.phi0[slot5][cxh] = h0v;
         }
     }
     __syncthreads();

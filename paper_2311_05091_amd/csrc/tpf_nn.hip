@@ -203,6 +203,112 @@ conv3x3_wgrad_k(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution, weight gradient with all nine taps per block.
+// The pixels are walked in segments of 32 consecutive pixels of one image
+// row.  Per segment a block stages dy (32 pixels x BM output channels) and
+// the input patch around it (3 rows x 34 pixels x 32 input channels) in LDS,
+// both transposed to pixel-fastest order; the patch is stored three times,
+// shifted by one column each, so that every tap's operand is an aligned
+// 16-byte LDS read.  Each dy fragment then feeds 9 (taps) x 2 (ci groups)
+// MFMA tiles.  Splits over segments give partial sums, added later in a
+// fixed order.  Requires W % 32 == 0.
+// ---------------------------------------------------------------------------
+template <int BM>
+__global__ void __launch_bounds__(256)
+conv3x3_wgrad9_k(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy, int H, int W, int Cin,
+                 int Cout, int nseg, int segs_per_split, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][40];        // [co][px]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[3][32][3][40];  // [column shift][ci][row][px]
+    constexpr int CG = BM / 16;          // output-channel groups of 16
+    constexpr int TPW = CG * 2 * 9 / 4;  // MFMA tiles per wave: 18 (BM = 64) or 9 (BM = 32)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int co0 = blockIdx.x * BM, ci0 = blockIdx.y * 32;
+    const int s0 = blockIdx.z * segs_per_split, s1 = min(nseg, s0 + segs_per_split);
+    const int segs_row = W / 32;
+    // wave -> (output-channel group, first ci group)
+    const int cg = BM == 64 ? wave : (wave & 1);
+    const int gg = BM == 64 ? 0 : (wave >> 1);
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int sg = s0; sg < s1; ++sg) {
+        const int n = sg / (H * segs_row);
+        const int rr = sg - n * H * segs_row;
+        const int yy = rr / segs_row, xs0 = (rr - yy * segs_row) * 32;
+        // dy tile: thread -> (pixel, 8 output channels)
+        constexpr int TPP = BM / 8;
+        const bool aload = tid < 32 * TPP;
+        const int apx = tid / TPP, aseg = (tid % TPP) * 8;
+        uint4 av = make_uint4(0, 0, 0, 0);
+        if (aload)
+            av = *(const uint4*)(dy + ((size_t)(n * H + yy) * W + xs0 + apx) * Cout + co0 + aseg);
+        // input patch: 3 rows x 34 columns x 4 groups of 8 channels = 408 items
+        uint4 bv[2];
+        int bit[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int it = tid + 256 * k;
+            bit[k] = it;
+            bv[k] = make_uint4(0, 0, 0, 0);
+            if (it < 408) {
+                const int r = it / 136, rem = it - r * 136;
+                const int c = rem >> 2, q = rem & 3;
+                const int sy = yy - 1 + r, sx = xs0 - 1 + c;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                    bv[k] = *(const uint4*)(x + ((size_t)(n * H + sy) * W + sx) * Cin + ci0 + 8 * q);
+            }
+        }
+        __syncthreads();
+        if (aload) {
+            const uint16_t* e = (const uint16_t*)&av;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[aseg + j][apx] = e[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int it = bit[k];
+            if (it < 408) {
+                const int r = it / 136, rem = it - r * 136;
+                const int c = rem >> 2, q = rem & 3;
+                const uint16_t* e = (const uint16_t*)&bv[k];
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int px = c - dx;
+                    if (px >= 0 && px < 32) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) Bs[dx][8 * q + j][r][px] = e[j];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const bf16x8 a = as_bf16x8(*(const uint4*)&As[16 * cg + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) {
+            // tile k -> (tap, ci group)
+            const int g = BM == 64 ? (k / 9) : gg;
+            const int tap = BM == 64 ? (k % 9) : k;
+            const int ky = tap / 3, kx = tap % 3;
+            const bf16x8 b = as_bf16x8(*(const uint4*)&Bs[kx][16 * g + (lane & 15)][ky][(lane >> 4) * 8]);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+        }
+    }
+    float* out = part + (size_t)blockIdx.z * Cout * 9 * Cin;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        const int g = BM == 64 ? (k / 9) : gg;
+        const int tap = BM == 64 ? (k % 9) : k;
+        const int ci = ci0 + 16 * g + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = co0 + 16 * cg + 4 * (lane >> 4) + i;
+            out[((size_t)co * 9 + tap) * Cin + ci] = acc[k][i];
+        }
+    }
+}
+
 __global__ void sum_splits_k(const float* __restrict__ part, int splits, int64_t n, float* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -534,6 +640,18 @@ int wgrad_splits(int64_t P) {
     return (int)s;
 }
 
+// Segments (32 pixels of one row) per split of the nine-tap weight gradient:
+// about 2048 blocks in all, at least 16 segments per block.
+int wgrad9_segs_per_split(int64_t nseg, int Cin, int Cout) {
+    const int bm = Cout % 64 == 0 ? 64 : 32;
+    const int64_t nxy = (int64_t)(Cout / bm) * (Cin / 32);
+    int64_t splits = (2048 + nxy - 1) / nxy;
+    const int64_t max_splits = nseg / 16 > 0 ? nseg / 16 : 1;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    return (int)((nseg + splits - 1) / splits);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -573,10 +691,17 @@ extern "C" int tpfnn_weight_flip(const uint16_t* w, int32_t Cout, int32_t Cin, u
 
 extern "C" size_t tpfnn_wgrad_workspace(int32_t N, int32_t H, int32_t W, int32_t Cin, int32_t Cout) {
     const int64_t P = (int64_t)N * H * W;
-    const int S = wgrad_splits(P);
-    const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
-    const int nb = (int)((P + chunk - 1) / chunk);
-    const size_t wpart = (size_t)nb * Cout * 9 * Cin * sizeof(float);
+    size_t nb;
+    if (W % 32 == 0 && Cin > 0 && Cout > 0) {
+        const int64_t nseg = P / 32;
+        const int sps = wgrad9_segs_per_split(nseg, Cin, Cout);
+        nb = (size_t)((nseg + sps - 1) / sps);
+    } else {
+        const int S = wgrad_splits(P);
+        const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
+        nb = (size_t)((P + chunk - 1) / chunk);
+    }
+    const size_t wpart = nb * Cout * 9 * Cin * sizeof(float);
     const size_t bpart = (size_t)((P + kBiasPix - 1) / kBiasPix) * Cout * sizeof(float);
     return wpart + bpart + 256;
 }
@@ -590,22 +715,38 @@ extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_
     if (db && 256 % Cout) return kEinval;
     const int64_t P = (int64_t)N * H * W;
     if (P > 0x7fffffff) return kEinval;
-    const int S = wgrad_splits(P);
-    const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
-    const int nb = (int)((P + chunk - 1) / chunk);
     float* wpart = (float*)work;
-    float* bpart = wpart + (size_t)nb * Cout * 9 * Cin;
     hipStream_t st = (hipStream_t)stream;
     const int ncb = Cin / 32;
-    if (Cout % 64 == 0) {
-        dim3 g(Cout / 64, 9 * ncb, nb);
-        hipLaunchKernelGGL(conv3x3_wgrad_k<64>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
-                           wpart);
+    int nb;
+    if (W % 32 == 0) {
+        const int64_t nseg = P / 32;
+        const int sps = wgrad9_segs_per_split(nseg, Cin, Cout);
+        nb = (int)((nseg + sps - 1) / sps);
+        if (Cout % 64 == 0) {
+            dim3 g(Cout / 64, ncb, nb);
+            hipLaunchKernelGGL(conv3x3_wgrad9_k<64>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)nseg, sps,
+                               wpart);
+        } else {
+            dim3 g(Cout / 32, ncb, nb);
+            hipLaunchKernelGGL(conv3x3_wgrad9_k<32>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)nseg, sps,
+                               wpart);
+        }
     } else {
-        dim3 g(Cout / 32, 9 * ncb, nb);
-        hipLaunchKernelGGL(conv3x3_wgrad_k<32>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
-                           wpart);
+        const int S = wgrad_splits(P);
+        const int chunk = (int)((P + S - 1) / S + 31) / 32 * 32;
+        nb = (int)((P + chunk - 1) / chunk);
+        if (Cout % 64 == 0) {
+            dim3 g(Cout / 64, 9 * ncb, nb);
+            hipLaunchKernelGGL(conv3x3_wgrad_k<64>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
+                               wpart);
+        } else {
+            dim3 g(Cout / 32, 9 * ncb, nb);
+            hipLaunchKernelGGL(conv3x3_wgrad_k<32>, g, dim3(256), 0, st, x, dy, H, W, Cin, Cout, (int)P, chunk,
+                               wpart);
+        }
     }
+    float* bpart = wpart + (size_t)nb * Cout * 9 * Cin;
     if (hipGetLastError() != hipSuccess) return kEdevice;
     const int64_t nw = (int64_t)Cout * 9 * Cin;
     hipLaunchKernelGGL(sum_splits_k, grid1(nw), dim3(256), 0, st, wpart, nb, nw, dw);

@@ -114,8 +114,11 @@ def test_conv_input_gradient_via_flipped_weights():
     assert np.all(np.abs(got - ref) <= 2 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 64), (1, 32, 32, 64, 32), (4, 8, 8, 128, 256)])
+@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 64), (1, 32, 32, 64, 32), (4, 8, 8, 128, 256),
+                                             (2, 8, 64, 32, 64), (1, 4, 32, 256, 256), (3, 16, 32, 32, 32)])
 def test_conv_weight_gradient(N, H, W, Cin, Cout):
+    """Rows of width a multiple of 32 take the nine-tap kernel, the others the
+    per-tap one; both against the FP64 oracle."""
     _say("wgrad", N, H, W, Cin, Cout)
     torch = _torch()
     lib = _lib()
