@@ -26,13 +26,17 @@ struct TileShape {
 // LDS window); 8-11: strip kernel (one wavefront marching down a 64-column
 // strip of ty rows); 12-14: pipelined strip kernel (one wavefront per
 // 60-column strip, next row's loads in flight during the current row);
-// 15-16: strip kernel compiled for five wavefronts per SIMD.
+// 15-16: strip kernel compiled for five wavefronts per SIMD; 17, 18, 20:
+// groups of 4 or 2 strip wavefronts per workgroup advancing in lockstep
+// (groups of 8 would need more than the 64 KB of LDS a workgroup may hold in
+// FP64 with the S flux).
 static const TileShape kTiles[] = {{1, 64, 4, 256},  {2, 64, 8, 256},   {3, 64, 16, 256},
                                    {4, 128, 8, 256}, {5, 32, 8, 256},   {6, 64, 32, 256},
                                    {7, 128, 16, 256}, {8, 64, 16, 64},  {9, 64, 32, 64},
                                    {10, 64, 64, 64}, {11, 64, 128, 64}, {12, 60, 16, 64},
                                    {13, 60, 32, 64}, {14, 60, 64, 64}, {15, 64, 32, 64},
-                                   {16, 64, 16, 64}};
+                                   {16, 64, 16, 64}, {17, 256, 32, 256}, {18, 128, 32, 128},
+                                   {20, 256, 16, 256}};
 static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 static const int kDefaultTile = 9;
 
@@ -308,6 +312,13 @@ static hipError_t launch_strip_t(tpf_ctx* c, int t0, int ntiles, int offset, dou
     return hipGetLastError();
 }
 
+template <typename T, int CH, bool S, int MODE, int NW>
+static hipError_t launch_strip_group_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
+    hipLaunchKernelGGL((strip_group_kernel<T, CH, S, MODE, NW>), dim3(ntiles), dim3(64 * NW), 0, c->stream,
+                       c->d_doms, c->d_tiles + t0, ntiles, offset, mom);
+    return hipGetLastError();
+}
+
 template <typename T, int CH, bool S, int MODE>
 static hipError_t launch_strip_o5_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
     hipLaunchKernelGGL((strip_kernel_o5<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
@@ -325,6 +336,9 @@ static hipError_t launch_strip2_t(tpf_ctx* c, int t0, int ntiles, int offset, do
 template <typename T, bool S, int MODE>
 static hipError_t launch_step_shape(tpf_ctx* c, int code, int t0, int n, int offset, double* mom) {
     switch (code) {
+        case 17: return launch_strip_group_t<T, 32, S, MODE, 4>(c, t0, n, offset, mom);
+        case 18: return launch_strip_group_t<T, 32, S, MODE, 2>(c, t0, n, offset, mom);
+        case 20: return launch_strip_group_t<T, 16, S, MODE, 4>(c, t0, n, offset, mom);
         case 15: return launch_strip_o5_t<T, 32, S, MODE>(c, t0, n, offset, mom);
         case 16: return launch_strip_o5_t<T, 16, S, MODE>(c, t0, n, offset, mom);
         case 12: return launch_strip2_t<T, 16, S, MODE>(c, t0, n, offset, mom);
@@ -587,7 +601,11 @@ static int reduce(tpf_ctx* c, const std::vector<int>& which, bool update_snap) {
 extern "C" int tpf_create(tpf_ctx** out, int32_t precision, void* hip_stream) {
     if (!out || (precision != 32 && precision != 64)) return TPF_EINVAL;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return TPF_EDEVICE;
+    const hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        std::fprintf(stderr, "tpf: no usable device (%s, %d devices)\n", hipGetErrorString(e), ndev);
+        return TPF_EDEVICE;
+    }
     tpf_ctx* c = new tpf_ctx();
     c->precision = precision;
     c->stream = (hipStream_t)hip_stream;

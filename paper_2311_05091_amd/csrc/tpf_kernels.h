@@ -493,7 +493,7 @@ __device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S
     const KConst<T> K = kconst<T>(d);
     const int cur = (d.parity + step_offset) & 1;
     const bool dS = HAS_S && d.has_s;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     uint32_t cb[3] = {0, 0, 0}, hb[3] = {0, 0, 0};
     if constexpr (PX) {
         wrap_cols<T>(x0 + lane, d.nx, cb);
@@ -601,6 +601,26 @@ __global__ void __launch_bounds__(64)
 strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
              int step_offset, double* __restrict__ mom_out) {
     strip_body<T, CH, HAS_S, MODE>(doms, tiles, ntiles, step_offset, mom_out);
+}
+
+// NW wavefronts per workgroup, each marching its own 64-column strip of a
+// (64 NW)-column tile.  The two barriers of every strip iteration are then
+// workgroup barriers, so the NW strips advance row by row in lockstep and the
+// columns that neighbouring strips share (their stencil and pull halos) are
+// read while the other strip's wavefront holds the same cache lines.
+template <typename T, int CH, bool HAS_S, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
+strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+                   int step_offset, double* __restrict__ mom_out) {
+    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
+    __shared__ StripShared<T, HAS_S> sh[NW];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int4 tile = tiles[t];
+    const DomDev& d = doms[tile.x];
+    if (!d.live && MODE == kModeStep) return;
+    const int w = threadIdx.x >> 6;
+    strip_tile<T, CH, HAS_S, MODE>(d, sh[w], tile.y + 64 * w, tile.z, step_offset, mom_out);
 }
 
 // Same kernel compiled for five wavefronts per SIMD (fewer registers, a few

@@ -45,6 +45,20 @@ class DomainParams(C.Structure):
 
 _lib = None
 _D = C.POINTER(C.c_double)
+
+
+def init_torch_device():
+    """Initialises torch's HIP runtime (when a GPU is present) before a HIP
+    library of this package is loaded.  torch carries its own HIP runtime; a
+    library loaded into the process before torch has initialised the device
+    finds no device once torch has (measured: tpf_create then reports zero
+    devices), while the other order works."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 _I32 = C.POINTER(C.c_int32)
 _I64 = C.POINTER(C.c_int64)
 
@@ -57,6 +71,7 @@ def library() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("HIP library %s is not built; run paper_2311_05091_amd/build.py "
                            "(there is no CPU fallback)" % LIB_PATH)
+    init_torch_device()
     lib = C.CDLL(LIB_PATH)
     V = C.c_void_p
     sig = {

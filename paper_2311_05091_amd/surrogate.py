@@ -44,6 +44,8 @@ def nnlib() -> C.CDLL:
         return _nn
     if not os.path.exists(NN_LIB_PATH):
         raise RuntimeError("HIP library %s is not built; run paper_2311_05091_amd/build.py" % NN_LIB_PATH)
+    from .lbm import init_torch_device
+    init_torch_device()
     lib = C.CDLL(NN_LIB_PATH)
     sig = {
         "tpfnn_mfma_selftest": [V, V, V, V],

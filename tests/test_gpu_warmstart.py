@@ -1,0 +1,72 @@
+"""The learned warm start end to end at a small scale (run on an MI355X):
+batched sweep to a tolerance, dataset, two epochs of training, gate
+calibration, and the plain-vs-learned evaluation.  Checks the bookkeeping
+(step counts, retirement, fallbacks) and that the warm-started runs reach the
+same tolerance from a mass-exact initial field; the speed-up itself is
+measured by the full pipeline, not here."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2311_05091_amd import geometry as G
+from paper_2311_05091_amd import warmstart as W
+from paper_2311_05091_amd.lbm import Context, TPF_ENAN
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def test_warm_start_pipeline_small(tmp_path):
+    _say("warm start pipeline")
+    specs = G.batched_sweep(n_domains=10, smin=96, smax=160, seed0=77)
+    sw = W.sweep(specs, tol=1e-4, check_every=50, max_steps=4000)
+    assert len(sw["phi1"]) == 10 and (np.asarray(sw["steps"]) > 0).all()
+    assert (np.asarray(sw["steps"]) <= 4000).all()
+    for sp, phi in zip(specs, sw["phi1"]):
+        assert phi.shape == (sp.ny, sp.nx)
+    data = W.build_dataset(specs[:8], sw["phi1"][:8], sw["status"][:8])
+    assert data["phi0"].shape[1:] == (256, 256) and data["target"].min() >= 0.0 and data["target"].max() <= 1.0
+    net = W.train(data, epochs=2, batch=4, lr=5e-4, log=lambda m: None)
+    assert len(net.history) == 2 and np.isfinite(net.history).all()
+    gate = W.calibrate_gate(net, specs[8:], sw["phi1"][8:])
+    assert 0.0 <= gate < 2.0
+    path = str(tmp_path / "w.npz")
+    W.save_params(net, path, gate)
+    params, g2 = W.load_params(path)
+    assert g2 == pytest.approx(gate) and set(params) == set(net.params_numpy())
+    held = G.held_out_set(n_domains=4, s=128, seed0=900)
+    ev = W.evaluate(net, held, tol=1e-4, check_every=50, max_steps=4000, gate=gate, log=lambda m: None)
+    pd = ev["per_domain"]
+    assert len(pd["plain_steps"]) == 4 and len(pd["learned_steps"]) == 4
+    assert ev["learned_nan"] == 0 and ev["plain_nan"] == 0
+    assert all(0 < s <= 4000 for s in pd["plain_steps"]) and all(0 < s <= 8000 for s in pd["learned_steps"])
+    assert 0 <= ev["gated_to_plain"] <= 4
+
+
+def test_warm_start_field_is_mass_exact_and_bounded():
+    """A warm-start field from an arbitrary prediction keeps sum(phi1) and
+    stays within [0, 1 - phi0]; a domain started from it runs and conserves
+    the mass."""
+    from paper_2311_05091_amd import surrogate as S
+    _say("warm start field")
+    sp = G.held_out_set(n_domains=1, s=128, seed0=901)[0]
+    rng = np.random.default_rng(5)
+    pred = np.clip(0.5 + 0.4 * rng.normal(size=(256, 256)), 0.0, 1.0).astype(np.float32)
+    target = float(np.sum(sp.phi1))
+    f = S.warm_start_field(pred, sp.phi0, target)
+    assert abs(f.sum() - target) <= 1e-9 * target
+    assert (f >= 0).all() and (f <= 1.0 - sp.phi0 + 1e-6).all()
+    ctx = Context(precision=32)
+    ctx.add_domain(sp)
+    ctx.finalize()
+    ctx.set_phi1(0, f)
+    ctx.step(200)
+    d = ctx.diag(0)
+    assert d["status"] != TPF_ENAN
+    assert abs(d["mass"] - target) <= 1e-5 * target
+    ctx.close()
