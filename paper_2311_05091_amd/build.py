@@ -1,4 +1,6 @@
-"""Builds the HIP library libtpf.so for gfx950 with hipcc (in-tree)."""
+"""Builds the HIP libraries libtpf.so and libtpf_nn.so for gfx950 with hipcc
+(in-tree).  libtpf.so is compiled from three translation units in parallel
+(the host side and the FP32 and FP64 kernel instances) and linked."""
 from __future__ import annotations
 
 import os
@@ -14,9 +16,11 @@ NNLIB = os.path.join(PKG, "libtpf_nn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled on purpose: the compiler must not form
 # v_pk_* FP32 operations
-COMMON = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+COMMON = FLAGS + ["-shared"]
+LBM_SOURCES = ("tpf_api.hip", "tpf_launch_f32.hip", "tpf_launch_f64.hip")
 
 
 def _compile(sources, out, extra=()):
@@ -28,7 +32,21 @@ def _compile(sources, out, extra=()):
 
 
 def build_lbm() -> str:
-    return _compile([os.path.join(CSRC, "tpf_api.hip")], LIB)
+    """Compiles the translation units of libtpf.so concurrently, then links."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs, objs = [], []
+    for src in LBM_SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        objs.append(obj)
+        procs.append(subprocess.Popen([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    failed = [p.args for p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
 
 
 def build_nn() -> str:
@@ -39,10 +57,24 @@ def build_nn() -> str:
 
 
 def build_all():
+    """Both libraries; the surrogate library compiles while libtpf.so does."""
+    import threading
+    res = {}
+
+    def nn():
+        try:
+            res["nn"] = build_nn()
+        except Exception as e:  # re-raised below
+            res["err"] = e
+
+    th = threading.Thread(target=nn)
+    th.start()
     out = [build_lbm()]
-    nn = build_nn()
-    if nn:
-        out.append(nn)
+    th.join()
+    if "err" in res:
+        raise res["err"]
+    if res.get("nn"):
+        out.append(res["nn"])
     return out
 
 

@@ -16,6 +16,7 @@
 
 #include "tpf.h"
 #include "tpf_kernels.h"
+#include "tpf_launch.h"
 
 namespace tpf {
 
@@ -296,94 +297,18 @@ static size_t total_bytes(tpf_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Launch helpers
+// Launch helpers (the kernel instances live in tpf_launch_f32/f64.hip)
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, bool S, int MODE>
-static hipError_t launch_step_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
-    hipLaunchKernelGGL((step_kernel<T, TX, TY, 256, S, MODE>), dim3(ntiles), dim3(256), 0, c->stream,
-                       c->d_doms, c->d_tiles + t0, ntiles, offset, mom);
-    return hipGetLastError();
-}
-
-template <typename T, int CH, bool S, int MODE>
-static hipError_t launch_strip_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
-    hipLaunchKernelGGL((strip_kernel<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
-                       c->d_tiles + t0, ntiles, offset, mom);
-    return hipGetLastError();
-}
-
-template <typename T, int CH, bool S, int MODE, int NW>
-static hipError_t launch_strip_group_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
-    hipLaunchKernelGGL((strip_group_kernel<T, CH, S, MODE, NW>), dim3(ntiles), dim3(64 * NW), 0, c->stream,
-                       c->d_doms, c->d_tiles + t0, ntiles, offset, mom);
-    return hipGetLastError();
-}
-
-template <typename T, int CH, bool S, int MODE>
-static hipError_t launch_strip_o5_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
-    hipLaunchKernelGGL((strip_kernel_o5<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
-                       c->d_tiles + t0, ntiles, offset, mom);
-    return hipGetLastError();
-}
-
-template <typename T, int CH, bool S, int MODE>
-static hipError_t launch_strip2_t(tpf_ctx* c, int t0, int ntiles, int offset, double* mom) {
-    hipLaunchKernelGGL((strip2_kernel<T, CH, S, MODE>), dim3(ntiles), dim3(64), 0, c->stream, c->d_doms,
-                       c->d_tiles + t0, ntiles, offset, mom);
-    return hipGetLastError();
-}
-
-template <typename T, bool S, int MODE>
-static hipError_t launch_step_shape(tpf_ctx* c, int code, int t0, int n, int offset, double* mom) {
-    switch (code) {
-        case 17: return launch_strip_group_t<T, 32, S, MODE, 4>(c, t0, n, offset, mom);
-        case 18: return launch_strip_group_t<T, 32, S, MODE, 2>(c, t0, n, offset, mom);
-        case 20: return launch_strip_group_t<T, 16, S, MODE, 4>(c, t0, n, offset, mom);
-        case 15: return launch_strip_o5_t<T, 32, S, MODE>(c, t0, n, offset, mom);
-        case 16: return launch_strip_o5_t<T, 16, S, MODE>(c, t0, n, offset, mom);
-        case 12: return launch_strip2_t<T, 16, S, MODE>(c, t0, n, offset, mom);
-        case 13: return launch_strip2_t<T, 32, S, MODE>(c, t0, n, offset, mom);
-        case 14: return launch_strip2_t<T, 64, S, MODE>(c, t0, n, offset, mom);
-        case 8: return launch_strip_t<T, 16, S, MODE>(c, t0, n, offset, mom);
-        case 9: return launch_strip_t<T, 32, S, MODE>(c, t0, n, offset, mom);
-        case 10: return launch_strip_t<T, 64, S, MODE>(c, t0, n, offset, mom);
-        case 11: return launch_strip_t<T, 128, S, MODE>(c, t0, n, offset, mom);
-        case 1: return launch_step_t<T, 64, 4, S, MODE>(c, t0, n, offset, mom);
-        case 2: return launch_step_t<T, 64, 8, S, MODE>(c, t0, n, offset, mom);
-        case 3: return launch_step_t<T, 64, 16, S, MODE>(c, t0, n, offset, mom);
-        case 4: return launch_step_t<T, 128, 8, S, MODE>(c, t0, n, offset, mom);
-        case 5: return launch_step_t<T, 32, 8, S, MODE>(c, t0, n, offset, mom);
-        case 6: return launch_step_t<T, 64, 32, S, MODE>(c, t0, n, offset, mom);
-        case 7: return launch_step_t<T, 128, 16, S, MODE>(c, t0, n, offset, mom);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename T, int MODE>
-static hipError_t launch_group(tpf_ctx* c, bool S, int t0, int n, int offset, double* mom) {
-    if (n <= 0) return hipSuccess;
-    return S ? launch_step_shape<T, true, MODE>(c, c->tile_code, t0, n, offset, mom)
-             : launch_step_shape<T, false, MODE>(c, c->tile_code, t0, n, offset, mom);
-}
-
 // Launches the step (or moments) kernel over a tile table whose first n_noS
 // tiles belong to domains without S and the rest to domains with S.
 static hipError_t launch_step(tpf_ctx* c, int mode, int ntiles, int n_noS, int offset, double* mom) {
-    hipError_t e;
-    if (c->precision == 32) {
-        if (mode == kModeStep) {
-            if ((e = launch_group<float, kModeStep>(c, false, 0, n_noS, offset, mom))) return e;
-            return launch_group<float, kModeStep>(c, true, n_noS, ntiles - n_noS, offset, mom);
-        }
-        if ((e = launch_group<float, kModeMoments>(c, false, 0, n_noS, offset, mom))) return e;
-        return launch_group<float, kModeMoments>(c, true, n_noS, ntiles - n_noS, offset, mom);
-    }
-    if (mode == kModeStep) {
-        if ((e = launch_group<double, kModeStep>(c, false, 0, n_noS, offset, mom))) return e;
-        return launch_group<double, kModeStep>(c, true, n_noS, ntiles - n_noS, offset, mom);
-    }
-    if ((e = launch_group<double, kModeMoments>(c, false, 0, n_noS, offset, mom))) return e;
-    return launch_group<double, kModeMoments>(c, true, n_noS, ntiles - n_noS, offset, mom);
+    auto run = c->precision == 32 ? launch_tiles_f32 : launch_tiles_f64;
+    TileLaunch a{c->stream, c->d_doms, c->d_tiles, n_noS, offset, mom};
+    hipError_t e = run(c->tile_code, false, mode, a);
+    if (e != hipSuccess) return e;
+    a.tiles = c->d_tiles + n_noS;
+    a.ntiles = ntiles - n_noS;
+    return run(c->tile_code, true, mode, a);
 }
 
 // Host -> device upload of all descriptors (small; issued on the stream).
@@ -437,31 +362,6 @@ static int refresh_live(tpf_ctx* c) {
     return TPF_OK;
 }
 
-// Persistent launch over the current tile table (strip codes 8-10): one
-// kernel runs n steps of every live domain with per-domain step barriers.
-template <typename T, int CH, bool S>
-static int launch_persistent_t(tpf_ctx* c, int ntiles, int n) {
-    int per_cu = 0;
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_strip_kernel<T, CH, S>, 64, 0));
-    if (per_cu <= 0) per_cu = 1;
-    const int64_t total = (int64_t)n * ntiles;
-    const int grid = (int)std::min<int64_t>((int64_t)per_cu * c->n_cu, total);
-    hipLaunchKernelGGL((persistent_strip_kernel<T, CH, S>), dim3(grid), dim3(64), 0, c->stream, c->d_doms,
-                       c->d_tiles, ntiles, n, c->d_dom_tiles, c->d_ctl, c->d_done, 1 << 22);
-    HIP_OK(hipGetLastError());
-    return TPF_OK;
-}
-
-template <typename T, bool S>
-static int launch_persistent_shape(tpf_ctx* c, int ntiles, int n) {
-    switch (c->tile_code) {
-        case 8: return launch_persistent_t<T, 16, S>(c, ntiles, n);
-        case 9: return launch_persistent_t<T, 32, S>(c, ntiles, n);
-        case 10: return launch_persistent_t<T, 64, S>(c, ntiles, n);
-    }
-    return TPF_EINVAL;
-}
-
 static bool persistent_ok(const tpf_ctx* c) {
     return c->launch_mode == 1 && (c->tile_code == 8 || c->tile_code == 9 || c->tile_code == 10);
 }
@@ -489,11 +389,10 @@ static int run_persistent(tpf_ctx* c, int64_t n) {
             HIP_OK(hipEventCreate(&b));
             HIP_OK(hipEventRecord(a, c->stream));
         }
-        int rc = c->precision == 32 ? (S ? launch_persistent_shape<float, true>(c, ntiles, (int)m)
-                                         : launch_persistent_shape<float, false>(c, ntiles, (int)m))
-                                    : (S ? launch_persistent_shape<double, true>(c, ntiles, (int)m)
-                                         : launch_persistent_shape<double, false>(c, ntiles, (int)m));
-        if (rc) return rc;
+        const PersistentLaunch pl{c->stream, c->d_doms, c->d_tiles, ntiles, (int)m, c->d_dom_tiles,
+                                  c->d_ctl, c->d_done, c->n_cu, 1 << 22};
+        HIP_OK(c->precision == 32 ? launch_persistent_f32(c->tile_code, S, pl)
+                                  : launch_persistent_f64(c->tile_code, S, pl));
         if (c->timing) {
             HIP_OK(hipEventRecord(b, c->stream));
             c->ev_pool.push_back(a);

@@ -591,7 +591,7 @@ persistent_strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict_
     }
 }
 
-__global__ void zero_ints(int* __restrict__ p, int n) {
+static __global__ void zero_ints(int* __restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
@@ -941,7 +941,7 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
 
 // One thread per domain: folds the partials in a fixed order.
 // out: [dom][4] = mass, sum (phi1 - snap)^2, sum phi1^2, non-finite count.
-__global__ void reduce_final(const int* __restrict__ dom_list, int ndom, int nblk,
+static __global__ void reduce_final(const int* __restrict__ dom_list, int ndom, int nblk,
                              const double* __restrict__ partials, double* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ndom) return;

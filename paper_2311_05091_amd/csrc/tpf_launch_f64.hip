@@ -1,0 +1,11 @@
+// FP64 instances of the step-kernel launchers (see tpf_launch.h).
+#include "tpf_launch_impl.h"
+
+namespace tpf {
+hipError_t launch_tiles_f64(int code, bool with_s, int mode, const TileLaunch& a) {
+    return launch_tiles<double>(code, with_s, mode, a);
+}
+hipError_t launch_persistent_f64(int code, bool with_s, const PersistentLaunch& a) {
+    return launch_persistent<double>(code, with_s, a);
+}
+}  // namespace tpf
