@@ -148,7 +148,13 @@ int tpf_autotune(tpf_ctx* ctx, int32_t steps, double* best_ms);
  * Mode 1 applies to the strip tile codes 8-10; with any other tile code the
  * calls fall back to one launch per step.  Both modes give the same state.
  * A barrier wait that exceeds its spin bound (it cannot in a correct run)
- * makes the call return TPF_EDEVICE.  TPF_EINVAL for other modes. */
+ * makes the call return TPF_EDEVICE.  2 = one launch per step with the tile
+ * shape re-chosen at every call (and every residual check) from the live
+ * domains: the largest of the shapes 17, 9, 8, 2, 1 that still gives one
+ * wavefront per resident slot of the device, so that batches whose domains
+ * retire keep the device filled; the FP32 state may then differ from mode 0
+ * by rounding (the tile kernel contracts multiply-adds differently).
+ * TPF_EINVAL for other modes. */
 int tpf_set_launch_mode(tpf_ctx* ctx, int32_t mode);
 
 /* Bytes a step moves by definition per node: 18 population reads and writes,

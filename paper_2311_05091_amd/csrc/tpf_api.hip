@@ -418,8 +418,36 @@ static int run_persistent(tpf_ctx* c, int64_t n) {
 // Advances the live domains by n steps with one launch per step.  Domains
 // share the step count within the call, so each one's buffer parity is
 // (parity at entry + step index) & 1.
+// Launch mode 2: the tile shape follows the live work.  Candidates from the
+// largest tile down; the first whose tile table gives at least one
+// wavefront per resident slot (16 per compute unit) is taken, else the
+// smallest.  As domains retire, smaller tiles keep the device filled and a
+// step's latency short.
+static void adapt_tile(tpf_ctx* c) {
+    static const int kLadder[] = {17, 9, 8, 2, 1};
+    std::vector<int> live;
+    for (size_t i = 0; i < c->doms.size(); ++i)
+        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+    const int64_t slots = (int64_t)16 * std::max(c->n_cu, 1);
+    int pick = kLadder[sizeof(kLadder) / sizeof(kLadder[0]) - 1];
+    for (int code : kLadder) {
+        const TileShape* ts = find_tile(code);
+        int64_t waves = 0;
+        for (int di : live) {
+            const auto& p = c->doms[di].p;
+            waves += (int64_t)((p.nx + ts->tx - 1) / ts->tx) * ((p.ny + ts->ty - 1) / ts->ty) * (ts->threads / 64);
+        }
+        if (waves >= slots) {
+            pick = code;
+            break;
+        }
+    }
+    c->tile_code = pick;
+}
+
 static int run_steps(tpf_ctx* c, int64_t n) {
     if (n <= 0) return TPF_OK;
+    if (c->launch_mode == 2) adapt_tile(c);
     int rc = refresh_live(c);
     if (rc) return rc;
     if (c->live_list.empty()) return TPF_OK;
@@ -930,7 +958,7 @@ extern "C" int tpf_autotune(tpf_ctx* c, int32_t steps, double* best_ms) {
 }
 
 extern "C" int tpf_set_launch_mode(tpf_ctx* c, int32_t mode) {
-    if (!c || (mode != 0 && mode != 1)) return TPF_EINVAL;
+    if (!c || mode < 0 || mode > 2) return TPF_EINVAL;
     c->launch_mode = mode;
     return TPF_OK;
 }

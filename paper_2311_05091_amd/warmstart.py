@@ -34,7 +34,7 @@ def _sync():
 
 
 def sweep(specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int, precision: int = 32,
-          tile: Optional[int] = None, launch_mode: int = 0, group: int = 0, log=None) -> Dict:
+          tile: Optional[int] = None, launch_mode: int = 2, group: int = 0, log=None) -> Dict:
     """Advances the domains to r < tol (batched; converged domains retire) and
     returns their fields and statistics.  group > 0 runs consecutive groups of
     that many domains one after another (one context each) and logs after
@@ -178,7 +178,7 @@ def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: flo
 
 
 def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int,
-             precision: int = 32, launch_mode: int = 0, gate: float = 0.0, log=print) -> Dict:
+             precision: int = 32, launch_mode: int = 2, gate: float = 0.0, log=print) -> Dict:
     """Plain vs learned time to r < tol on the same held-out domains, each side
     one batch (converged domains retire).
 
@@ -295,7 +295,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--train-budget-s", type=float, default=240.0)
     ap.add_argument("--sweep-group", type=int, default=64, help="domains per sweep context (logged per group)")
-    ap.add_argument("--launch-mode", type=int, default=0, help="0: one launch per step; 1: persistent")
+    ap.add_argument("--launch-mode", type=int, default=2,
+                    help="0: one launch per step, fixed tiles; 1: persistent; 2: tiles follow the live work")
     ap.add_argument("--gate", type=float, default=-1.0,
                     help="warm-start gate (rel. L2 to the plain start); < 0: calibrated on validation domains")
     ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")

@@ -267,3 +267,30 @@ def test_persistent_launch_matches_per_step_launch(prec, tile):
     assert rc == lbm.TPF_EBUDGET and (steps == 100).all()
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_adaptive_tile_mode_matches_fixed_tiles(prec):
+    """Launch mode 2 re-chooses the tile shape from the live work at every
+    call: same state as fixed tiles up to the rounding differences between
+    the kernels (FP64 1e-13, FP32 2e-6 of the largest population), and
+    residual-driven runs retire domains as in mode 0."""
+    specs = _mixed_batch()
+    _say("adaptive", prec)
+    a = gpu_context(specs, precision=prec, tile=9)
+    a.step(60)
+    b = gpu_context(specs, precision=prec)
+    b.set_launch_mode(2)
+    b.step(60)
+    code, _, _ = b.tile()
+    assert code in (17, 9, 8, 2, 1)
+    tol = 1e-13 if prec == 64 else 2e-6
+    for i in range(len(specs)):
+        fa, ga = a.populations(i)
+        fb, gb = b.populations(i)
+        assert np.abs(fa - fb).max() <= tol * np.abs(fa).max()
+        assert np.abs(ga - gb).max() <= tol * max(np.abs(ga).max(), 1e-12)
+    rc, steps = b.run_to_residual(1e-30, check_every=20, max_steps=40)
+    assert rc == lbm.TPF_EBUDGET and (steps == 40).all()
+    a.close()
+    b.close()
