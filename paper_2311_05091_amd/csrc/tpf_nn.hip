@@ -309,12 +309,22 @@ conv3x3_wgrad9_k(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy
     }
 }
 
-__global__ void sum_splits_k(const float* __restrict__ part, int splits, int64_t n, float* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// out[i] = sum over k of part[k][i].  A block covers 64 outputs with four
+// waves, wave g adding splits g, g + 4, g + 8, ...; the four partial sums
+// are then added in order g = 0..3 (fixed order, deterministic).
+__global__ void __launch_bounds__(256)
+sum_splits_k(const float* __restrict__ part, int splits, int64_t n, float* __restrict__ out) {
+    __shared__ float red[4][64];
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + o;
     float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
-    out[i] = s;
+    if (i < n) {
+#pragma unroll 8
+        for (int k = g; k < splits; k += 4) s += part[(size_t)k * n + i];
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < n) out[i] = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
 }
 
 // db partials: block b sums pixels [b*kBiasPix, (b+1)*kBiasPix) for every
@@ -418,6 +428,58 @@ __global__ void upsample2_bwd_k(const uint16_t* __restrict__ dy, int N, int H, i
     const float s = bf2f(dy[b]) + bf2f(dy[b + C]) + bf2f(dy[b + (size_t)Wo * C]) +
                     bf2f(dy[b + (size_t)Wo * C + C]);
     dx[i] = f2bf(s);
+}
+
+// 16-byte (8-channel) versions of the copies and masks above, used when the
+// channel counts are multiples of 8.
+__global__ void relu_bwd_v8_k(const uint4* __restrict__ y, uint4* __restrict__ dy, int64_t n8) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const uint4 yv = y[i];
+    uint4 g = dy[i];
+    const uint32_t ys[4] = {yv.x, yv.y, yv.z, yv.w};
+    uint32_t gs[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!(bf2f((uint16_t)(ys[j] & 0xffffu)) > 0.f)) gs[j] &= 0xffff0000u;
+        if (!(bf2f((uint16_t)(ys[j] >> 16)) > 0.f)) gs[j] &= 0x0000ffffu;
+    }
+    dy[i] = make_uint4(gs[0], gs[1], gs[2], gs[3]);
+}
+
+__global__ void upsample2_fwd_v8_k(const uint4* __restrict__ x, int N, int H, int W, int C8,
+                                   uint4* __restrict__ y) {
+    const int Ho = 2 * H, Wo = 2 * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * Ho * Wo * C8) return;
+    const int c = (int)(i % C8);
+    int64_t r = i / C8;
+    const int xo = (int)(r % Wo);
+    r /= Wo;
+    const int yo = (int)(r % Ho);
+    const int n = (int)(r / Ho);
+    y[i] = x[((size_t)(n * H + yo / 2) * W + xo / 2) * C8 + c];
+}
+
+__global__ void concat_v8_k(const uint4* __restrict__ a, int Ca8, const uint4* __restrict__ b, int Cb8,
+                            int64_t npix, uint4* __restrict__ y) {
+    const int C8 = Ca8 + Cb8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C8) return;
+    const int64_t p = i / C8;
+    const int c = (int)(i % C8);
+    y[i] = c < Ca8 ? a[p * Ca8 + c] : b[p * Cb8 + (c - Ca8)];
+}
+
+__global__ void split_v8_k(const uint4* __restrict__ dy, int Ca8, int Cb8, int64_t npix, uint4* __restrict__ da,
+                           uint4* __restrict__ db) {
+    const int C8 = Ca8 + Cb8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C8) return;
+    const int64_t p = i / C8;
+    const int c = (int)(i % C8);
+    if (c < Ca8) da[p * Ca8 + c] = dy[i];
+    else db[p * Cb8 + (c - Ca8)] = dy[i];
 }
 
 __global__ void concat_k(const uint16_t* __restrict__ a, int Ca, const uint16_t* __restrict__ b, int Cb,
@@ -646,6 +708,7 @@ int wgrad9_segs_per_split(int64_t nseg, int Cin, int Cout) {
     const int bm = Cout % 64 == 0 ? 64 : 32;
     const int64_t nxy = (int64_t)(Cout / bm) * (Cin / 32);
     int64_t splits = (2048 + nxy - 1) / nxy;
+    if (splits > 512) splits = 512;  // bounds the partial sums the reduction reads
     const int64_t max_splits = nseg / 16 > 0 ? nseg / 16 : 1;
     if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
@@ -749,13 +812,14 @@ extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_
     float* bpart = wpart + (size_t)nb * Cout * 9 * Cin;
     if (hipGetLastError() != hipSuccess) return kEdevice;
     const int64_t nw = (int64_t)Cout * 9 * Cin;
-    hipLaunchKernelGGL(sum_splits_k, grid1(nw), dim3(256), 0, st, wpart, nb, nw, dw);
+    hipLaunchKernelGGL(sum_splits_k, dim3((unsigned)((nw + 63) / 64)), dim3(256), 0, st, wpart, nb, nw, dw);
     if (hipGetLastError() != hipSuccess) return kEdevice;
     if (db) {
         const int nbb = (int)((P + kBiasPix - 1) / kBiasPix);
         hipLaunchKernelGGL(bias_grad_part_k, dim3(nbb), dim3(256), 0, st, dy, (int)P, Cout, bpart);
         if (hipGetLastError() != hipSuccess) return kEdevice;
-        hipLaunchKernelGGL(sum_splits_k, grid1(Cout), dim3(256), 0, st, bpart, nbb, (int64_t)Cout, db);
+        hipLaunchKernelGGL(sum_splits_k, dim3((unsigned)((Cout + 63) / 64)), dim3(256), 0, st, bpart, nbb,
+                           (int64_t)Cout, db);
     }
     return launch_status();
 }
@@ -763,6 +827,11 @@ extern "C" int tpfnn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dy, int32_
 extern "C" int tpfnn_relu_bwd(const uint16_t* y, uint16_t* dy, int64_t n, void* stream) {
     if (!y || !dy || n < 0) return kEinval;
     if (n == 0) return kOk;
+    if (n % 8 == 0 && ((uintptr_t)y | (uintptr_t)dy) % 16 == 0) {
+        hipLaunchKernelGGL(relu_bwd_v8_k, grid1(n / 8), dim3(256), 0, (hipStream_t)stream, (const uint4*)y,
+                           (uint4*)dy, n / 8);
+        return launch_status();
+    }
     hipLaunchKernelGGL(relu_bwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, y, dy, n);
     return launch_status();
 }
@@ -787,6 +856,11 @@ extern "C" int tpfnn_upsample2_fwd(const uint16_t* x, int32_t N, int32_t H, int3
                                    void* stream) {
     if (!x || !y || N <= 0 || H <= 0 || W <= 0 || C <= 0) return kEinval;
     const int64_t n = (int64_t)N * 4 * H * W * C;
+    if (C % 8 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0) {
+        hipLaunchKernelGGL(upsample2_fwd_v8_k, grid1(n / 8), dim3(256), 0, (hipStream_t)stream, (const uint4*)x, N,
+                           H, W, C / 8, (uint4*)y);
+        return launch_status();
+    }
     hipLaunchKernelGGL(upsample2_fwd_k, grid1(n), dim3(256), 0, (hipStream_t)stream, x, N, H, W, C, y);
     return launch_status();
 }
@@ -803,6 +877,11 @@ extern "C" int tpfnn_concat(const uint16_t* a, int32_t Ca, const uint16_t* b, in
                             uint16_t* y, void* stream) {
     if (!a || !b || !y || Ca <= 0 || Cb <= 0 || npix <= 0) return kEinval;
     const int64_t n = npix * (Ca + Cb);
+    if (Ca % 8 == 0 && Cb % 8 == 0 && ((uintptr_t)a | (uintptr_t)b | (uintptr_t)y) % 16 == 0) {
+        hipLaunchKernelGGL(concat_v8_k, grid1(n / 8), dim3(256), 0, (hipStream_t)stream, (const uint4*)a, Ca / 8,
+                           (const uint4*)b, Cb / 8, npix, (uint4*)y);
+        return launch_status();
+    }
     hipLaunchKernelGGL(concat_k, grid1(n), dim3(256), 0, (hipStream_t)stream, a, Ca, b, Cb, npix, y);
     return launch_status();
 }
@@ -811,6 +890,11 @@ extern "C" int tpfnn_split(const uint16_t* dy, int32_t Ca, int32_t Cb, int64_t n
                            uint16_t* db, void* stream) {
     if (!dy || !da || !db || Ca <= 0 || Cb <= 0 || npix <= 0) return kEinval;
     const int64_t n = npix * (Ca + Cb);
+    if (Ca % 8 == 0 && Cb % 8 == 0 && ((uintptr_t)dy | (uintptr_t)da | (uintptr_t)db) % 16 == 0) {
+        hipLaunchKernelGGL(split_v8_k, grid1(n / 8), dim3(256), 0, (hipStream_t)stream, (const uint4*)dy, Ca / 8,
+                           Cb / 8, npix, (uint4*)da, (uint4*)db);
+        return launch_status();
+    }
     hipLaunchKernelGGL(split_k, grid1(n), dim3(256), 0, (hipStream_t)stream, dy, Ca, Cb, npix, da, db);
     return launch_status();
 }
