@@ -25,12 +25,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 
-# HBM traffic per launch of the step kernel (tile code 17: groups of four
-# 64 x 32 strips, FP32) on the porous 4096 x 2048 workload, from rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the factor a
-# plain copy kernel of known size gives (1.99974 and 1.0): 384936.9 KiB x
-# 1.99974 + 688128.1 KiB.  Reported only for that tile code, workload and
-# precision; removed whenever the kernel source changes after the counters
+# HBM traffic per launch of the step kernel on the porous 4096 x 2048
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+# scaled by the factors a plain copy kernel of known size gives (1.99974 and
+# 1.0): FP32 tile code 17 (groups of four 64 x 32 strips) 384936.9 KiB x
+# 1.99974 + 688128.1 KiB; FP64 tile code 9 919324.1 KiB x 1.99975 +
+# 1376256.1 KiB.  Reported only for those tile codes, workload and
+# precisions; removed whenever the kernel source changes after the counters
 # were taken.
 PMC_TRAFFIC_BYTES = {(17, 32, "porous_displacement_4096x2048"): 1.4929e9,
                      (9, 64, "porous_displacement_4096x2048"): 3.2918e9}
