@@ -282,7 +282,7 @@ def main(argv=None):
     import argparse
     import os
     ap = argparse.ArgumentParser(description="batched sweep -> surrogate training -> warm-start evaluation")
-    ap.add_argument("--train-domains", type=int, default=512)
+    ap.add_argument("--train-domains", type=int, default=768)
     ap.add_argument("--smin", type=int, default=128)
     ap.add_argument("--smax", type=int, default=512)
     ap.add_argument("--eval-domains", type=int, default=256)
@@ -290,10 +290,10 @@ def main(argv=None):
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--sweep-cap", type=int, default=60000)
     ap.add_argument("--eval-cap", type=int, default=100000)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=250)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=3e-4)
-    ap.add_argument("--train-budget-s", type=float, default=240.0)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--train-budget-s", type=float, default=300.0)
     ap.add_argument("--sweep-group", type=int, default=64, help="domains per sweep context (logged per group)")
     ap.add_argument("--launch-mode", type=int, default=2,
                     help="0: one launch per step, fixed tiles; 1: persistent; 2: tiles follow the live work")
