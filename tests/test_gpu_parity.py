@@ -124,21 +124,31 @@ def test_config1_fp64_5000_steps(orc):
 
 
 def test_config1_fp32_contact_angle(orc):
-    """FP32 offset storage: the contact angle after 5000 steps is within 0.5 deg of the
-    FP64 oracle's, and rel L2 errors of phi and u are small."""
+    """FP32 offset storage: after 5000 steps the contact angle is within 0.5 deg
+    of the FP64 oracle's, the Laplace pressure jump within 2%, the mass drift
+    below 1e-5, and the rel. L2 errors of phi and u small; all printed."""
     sp = G.flat_wall_droplet()
     _say("config1 fp32 5000")
     ctx = gpu_context([sp], precision=32)
     ctx.step(5000)
     phi_g, ux_g, uy_g, p_g = ctx.moments(0)
+    mass_g = ctx.diag(0)["mass"]
     sim = oracle_run(orc, sp, 5000)
     phi_o, ux_o, uy_o, p_o = sim.moments()
-    th_g = Me.droplet_on_flat_wall(phi_g, 7.5, sp.D)["theta_deg"]
-    th_o = Me.droplet_on_flat_wall(phi_o, 7.5, sp.D)["theta_deg"]
-    print("theta fp32 %.4f oracle %.4f" % (th_g, th_o))
-    assert abs(th_g - th_o) <= 0.5
-    assert rel_l2(phi_g, phi_o) <= 1e-3
-    assert rel_l2(np.stack([ux_g, uy_g]), np.stack([ux_o, uy_o])) <= 5e-2
+    mg = Me.droplet_on_flat_wall(phi_g, 7.5, sp.D)
+    mo = Me.droplet_on_flat_wall(phi_o, 7.5, sp.D)
+    dp_g = Me.laplace_jump(p_g, phi_g, (mg["xc"], mg["yc"]), mg["R"], sp.D)
+    dp_o = Me.laplace_jump(p_o, phi_o, (mo["xc"], mo["yc"]), mo["R"], sp.D)
+    e_phi = rel_l2(phi_g, phi_o)
+    e_u = rel_l2(np.stack([ux_g, uy_g]), np.stack([ux_o, uy_o]))
+    drift = (mass_g - sp.phi1.sum()) / sp.phi1.sum()
+    print("[config1] theta fp32 %.4f oracle %.4f | dp fp32 %.5e oracle %.5e | rel L2 phi %.2e u %.2e | "
+          "mass drift %.2e" % (mg["theta_deg"], mo["theta_deg"], dp_g, dp_o, e_phi, e_u, drift))
+    assert abs(mg["theta_deg"] - mo["theta_deg"]) <= 0.5
+    assert abs(dp_g - dp_o) <= 0.02 * abs(dp_o)
+    assert abs(drift) <= 1e-5
+    assert e_phi <= 1e-3
+    assert e_u <= 5e-2
     ctx.close()
 
 
