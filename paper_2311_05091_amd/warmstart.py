@@ -300,7 +300,7 @@ def main(argv=None):
     ap.add_argument("--gate", type=float, default=-1.0,
                     help="warm-start gate (rel. L2 to the plain start); < 0: calibrated on validation domains")
     ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")
-    ap.add_argument("--out", default="gpurun_out/warmstart")
+    ap.add_argument("--out", default="warmstart_out")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     logf = open(os.path.join(args.out, "log.jsonl"), "a")
