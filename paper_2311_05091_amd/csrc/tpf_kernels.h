@@ -620,7 +620,18 @@ strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ til
     const DomDev& d = doms[tile.x];
     if (!d.live && MODE == kModeStep) return;
     const int w = threadIdx.x >> 6;
-    strip_tile<T, CH, HAS_S, MODE>(d, sh[w], tile.y + 64 * w, tile.z, step_offset, mom_out);
+    const int x0 = tile.y + 64 * w;
+    if (x0 >= d.nx) {
+        // strip entirely beyond the domain's last column (a ragged tile): no
+        // work, but the wavefront keeps meeting the two barriers of every
+        // row of its group
+        for (int r = 0; r < CH + 4; ++r) {
+            __syncthreads();
+            __syncthreads();
+        }
+        return;
+    }
+    strip_tile<T, CH, HAS_S, MODE>(d, sh[w], x0, tile.z, step_offset, mom_out);
 }
 
 // Same kernel compiled for five wavefronts per SIMD (fewer registers, a few
