@@ -37,10 +37,10 @@ PMC_TRAFFIC_BYTES = {(17, 32, "porous_displacement_4096x2048"): 1.4925e9,
                      (9, 64, "porous_displacement_4096x2048"): 3.2918e9}
 
 
-def workload(name: str):
+def workload(name: str, nx: int = 4096, ny: int = 2048):
     from paper_2311_05091_amd import geometry as G
     if name == "porous_displacement":
-        return [G.porous_medium()], "porous_displacement_4096x2048"
+        return [G.porous_medium(nx=nx, ny=ny)], "porous_displacement_%dx%d" % (nx, ny)
     if name == "cylinder_droplet":
         return [G.cylinder_droplet()], "cylinder_droplet_1024x1024"
     if name == "flat_wall_droplet":
@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="porous_displacement")
+    ap.add_argument("--nx", type=int, default=4096, help="porous workload width")
+    ap.add_argument("--ny", type=int, default=2048, help="porous workload height")
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
     ap.add_argument("--launch-mode", type=int, default=0,
@@ -104,7 +106,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    specs, wname = workload(args.workload)
+    specs, wname = workload(args.workload, args.nx, args.ny)
     nodes = sum(s.nx * s.ny for s in specs)
     print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)
     ctx = Context(precision=args.precision)
@@ -114,7 +116,7 @@ def main():
     if args.tile:
         ctx.set_tile(args.tile)
     else:
-        ctx.autotune(steps=10)
+        ctx.autotune(steps=30)
     code, tx, ty = ctx.tile()
     if args.launch_mode:
         ctx.set_launch_mode(args.launch_mode)

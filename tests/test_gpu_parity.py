@@ -97,6 +97,34 @@ def test_every_tile_shape_consistent(orc):
                     assert np.abs(a - b).max() <= tol * np.abs(b).max(), (code, prec, other_fam)
 
 
+def test_group_codes_on_a_batch_of_ragged_domains():
+    """A group tile whose strips pass a domain's right edge keeps the
+    wavefronts of the missing strips meeting the barriers only.  A batch of
+    domains of 5, 3, 9 and 9 strips (groups of 4 and 2 with one to three
+    missing strips; periodic and walled; with and without S; ragged in y)
+    stepped under codes 17, 18 and 20 equals the single-strip code 9 bit for
+    bit, in both precisions."""
+    specs = [G.solid_disk_box(n=300, ny=40, Rs=9.0, R0=11.0, periodic_y=0, rho=(1.0, 1.0, 0.1),
+                              mu=(0.15, 0.15, 0.015)),
+             G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0),
+             G.solid_disk_box(n=540, ny=21, Rs=6.0, R0=7.0, periodic_y=1, rho=(1.0, 1.0, 0.1),
+                              mu=(0.15, 0.15, 0.015)),
+             G.solid_disk_box(n=520, ny=35, Rs=8.0, R0=9.0, periodic_y=0)]
+    for prec in (32, 64):
+        ref = None
+        for code in (9, 17, 18, 20):
+            _say("group batch", code, prec)
+            ctx = gpu_context(specs, precision=prec, tile=code)
+            ctx.step(30)
+            pops = [ctx.populations(i) for i in range(len(specs))]
+            ctx.close()
+            if ref is None:
+                ref = pops
+                continue
+            for i, ((f, g), (fr, gr)) in enumerate(zip(pops, ref)):
+                assert np.array_equal(f, fr) and np.array_equal(g, gr), (code, prec, i)
+
+
 def test_initial_state_matches_oracle(orc):
     sp = G.flat_wall_droplet(nx=70, ny=30, wall_rows=5, R0=10)
     _say("init", sp.nx, sp.ny)
