@@ -27,13 +27,15 @@ METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 
 # HBM traffic per launch of the step kernel on the porous 4096 x 2048
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
-# scaled by the factors a plain copy kernel of known size gives (1.99974 and
-# 1.0): FP32 tile code 17 (groups of four 64 x 32 strips) 384763.1 KiB x
-# 1.99974 + 688128.1 KiB; FP64 tile code 9 919324.1 KiB x 1.99975 +
-# 1376256.1 KiB.  Reported only for those tile codes, workload and
+# scaled by the factors a plain copy kernel of known size gives (1.99974 or
+# 1.99975, and 1.0): tile code 22 (groups of four 64 x 64 strips) FP32
+# 373850.4 KiB x 1.99974 + 688128.4 KiB, FP64 747348.4 KiB x 1.99975 +
+# 1376259.7 KiB; FP64 tile code 9 (single 64 x 32 strips) 919324.1 KiB x
+# 1.99975 + 1376256.1 KiB.  Reported only for those tile codes, workload and
 # precisions; removed whenever the kernel source changes after the counters
 # were taken.
-PMC_TRAFFIC_BYTES = {(17, 32, "porous_displacement_4096x2048"): 1.4925e9,
+PMC_TRAFFIC_BYTES = {(22, 32, "porous_displacement_4096x2048"): 1.4702e9,
+                     (22, 64, "porous_displacement_4096x2048"): 2.9397e9,
                      (9, 64, "porous_displacement_4096x2048"): 3.2918e9}
 
 

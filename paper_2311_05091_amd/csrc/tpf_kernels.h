@@ -609,11 +609,9 @@ strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, in
 // columns that neighbouring strips share (their stencil and pull halos) are
 // read while the other strip's wavefront holds the same cache lines.
 template <typename T, int CH, bool HAS_S, int MODE, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
-strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
-                   int step_offset, double* __restrict__ mom_out) {
-    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
-    __shared__ StripShared<T, HAS_S> sh[NW];
+__device__ __forceinline__ void strip_group_body(StripShared<T, HAS_S>* sh, const DomDev* __restrict__ doms,
+                                                 const int4* __restrict__ tiles, int ntiles, int step_offset,
+                                                 double* __restrict__ mom_out) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= ntiles) return;
     const int4 tile = tiles[t];
@@ -632,6 +630,29 @@ strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ til
         return;
     }
     strip_tile<T, CH, HAS_S, MODE>(d, sh[w], x0, tile.z, step_offset, mom_out);
+}
+
+// Compiled for four wavefronts per SIMD (at most 128 VGPRs): the FP32 step
+// fits without spills.
+template <typename T, int CH, bool HAS_S, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
+strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+                   int step_offset, double* __restrict__ mom_out) {
+    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
+    __shared__ StripShared<T, HAS_S> sh[NW];
+    strip_group_body<T, CH, HAS_S, MODE, NW>(sh, doms, tiles, ntiles, step_offset, mom_out);
+}
+
+// The same groups with the register budget left to the compiler (the FP64
+// step takes about 230 VGPRs, two wavefronts per SIMD), so the FP64 build
+// gets the shared halos without spilling.
+template <typename T, int CH, bool HAS_S, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW)
+strip_group_kernel_wide(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
+                        int step_offset, double* __restrict__ mom_out) {
+    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
+    __shared__ StripShared<T, HAS_S> sh[NW];
+    strip_group_body<T, CH, HAS_S, MODE, NW>(sh, doms, tiles, ntiles, step_offset, mom_out);
 }
 
 // Same kernel compiled for five wavefronts per SIMD (fewer registers, a few
