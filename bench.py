@@ -28,15 +28,15 @@ METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 # HBM traffic per launch of the step kernel on the porous 4096 x 2048
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
 # scaled by the factors a plain copy kernel of known size gives (1.99974 or
-# 1.99975, and 1.0): tile code 22 (groups of four 64 x 64 strips) FP32
-# 373850.4 KiB x 1.99974 + 688128.4 KiB, FP64 747348.4 KiB x 1.99975 +
-# 1376259.7 KiB; FP64 tile code 9 (single 64 x 32 strips) 919324.1 KiB x
-# 1.99975 + 1376256.1 KiB.  Reported only for those tile codes, workload and
-# precisions; removed whenever the kernel source changes after the counters
-# were taken.
-PMC_TRAFFIC_BYTES = {(22, 32, "porous_displacement_4096x2048"): 1.4702e9,
-                     (22, 64, "porous_displacement_4096x2048"): 2.9397e9,
-                     (9, 64, "porous_displacement_4096x2048"): 3.2918e9}
+# 1.99975, and 1.0), for groups of four 64 x 64 strips: FP32 tile code 23
+# (non-temporal population loads) 399588.1 KiB x 1.99974 + 688128.0 KiB;
+# FP64 tile code 22 750280.8 KiB x 1.99975 + 1376257.2 KiB; FP64 tile code 24
+# (non-temporal NS loads) 755688.1 KiB x 1.99974 + 1376257.9 KiB.  Reported
+# only for those tile codes, workload and precisions; removed whenever the
+# kernel source changes after the counters were taken.
+PMC_TRAFFIC_BYTES = {(23, 32, "porous_displacement_4096x2048"): 1.5229e9,
+                     (22, 64, "porous_displacement_4096x2048"): 2.9457e9,
+                     (24, 64, "porous_displacement_4096x2048"): 2.9567e9}
 
 
 def workload(name: str, nx: int = 4096, ny: int = 2048):

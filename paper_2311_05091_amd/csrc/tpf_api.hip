@@ -31,14 +31,17 @@ struct TileShape {
 // groups of 4 or 2 strip wavefronts per workgroup advancing in lockstep
 // (groups of 8 would need more than the 64 KB of LDS a workgroup may hold in
 // FP64 with the S flux); 21, 22: groups of 4 strips of 32 or 64 rows with
-// the register budget left to the compiler.
+// the register budget left to the compiler; 23, 24: code 22 with
+// non-temporal loads of the pulled populations of both lattices (23) or of
+// the NS lattice only (24).
 static const TileShape kTiles[] = {{1, 64, 4, 256},  {2, 64, 8, 256},   {3, 64, 16, 256},
                                    {4, 128, 8, 256}, {5, 32, 8, 256},   {6, 64, 32, 256},
                                    {7, 128, 16, 256}, {8, 64, 16, 64},  {9, 64, 32, 64},
                                    {10, 64, 64, 64}, {11, 64, 128, 64}, {12, 60, 16, 64},
                                    {13, 60, 32, 64}, {14, 60, 64, 64}, {15, 64, 32, 64},
                                    {16, 64, 16, 64}, {17, 256, 32, 256}, {18, 128, 32, 128},
-                                   {20, 256, 16, 256}, {21, 256, 32, 256}, {22, 256, 64, 256}};
+                                   {20, 256, 16, 256}, {21, 256, 32, 256}, {22, 256, 64, 256},
+                                   {23, 256, 64, 256}, {24, 256, 64, 256}};
 static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 static const int kDefaultTile = 9;
 

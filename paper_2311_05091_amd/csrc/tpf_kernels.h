@@ -300,12 +300,23 @@ struct StripShared {
     T psi[HAS_S ? 3 : 1][66];
 };
 
+// Load of a pulled population: non-temporal (NT) or plain.  Which is faster
+// depends on the tiling: within lockstep groups of 64-row strips NT loads
+// measured faster in FP32 (the DRAM streams run closer to copy speed, at the
+// price of a few halo columns read twice); where neighbouring strips run in
+// different workgroups the shared halo columns then miss the cache.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_pop(gptr<const T> p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Pulled populations of a node whose source columns x - 1, x, x + 1 are given
 // as byte offsets cb (wrapped periodically once per tile), in row y: the row
 // part of every source address is uniform across the wave (scalar), the
 // column part a per-lane offset.  A source row beyond a wall gives the
 // opposite population of the node itself (half-way bounce-back).
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&cb)[3], int y, int nx, int ny,
                                            int py, int N, T (&out)[9]) {
     int ym = y - 1, yp = y + 1;
@@ -320,7 +331,7 @@ __device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&c
         // source row of population q is y - cy_q: rows[1 - cy_q]
         gptr<const T> rows[3] = {fin + (int64_t)ym * nx, fin + (int64_t)y * nx, fin + (int64_t)yp * nx};
 #pragma unroll
-        for (int q = 0; q < 9; ++q) out[q] = *at_bytes(rows[1 - cy_of(q)] + (int64_t)q * N, cb[1 - cx_of(q)]);
+        for (int q = 0; q < 9; ++q) out[q] = ld_pop<T, NT>(at_bytes(rows[1 - cy_of(q)] + (int64_t)q * N, cb[1 - cx_of(q)]));
         return;
     }
 #pragma unroll
@@ -344,7 +355,7 @@ __device__ __forceinline__ void wrap_cols(int x, int nx, uint32_t (&cb)[3]) {
 // each lane's source columns are fixed for the whole tile (cb: own column,
 // hb: the halo column of lanes 0..3) and every load uses scalar-base
 // addressing; otherwise the general pull with per-lane wall handling.
-template <typename T, int CH, bool HAS_S, int MODE, bool PX>
+template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT = 0>
 __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, StripShared<T, HAS_S>& sh, int r, int x0,
                                            int y0, int lane, int cur, bool dS, const uint32_t (&cb)[3],
                                            const uint32_t (&hb)[3], T (&fL)[9], T (&fU)[9],
@@ -369,10 +380,10 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     const int cxh = lane < 2 ? lane : 64 + lane;   // halo cells 0, 1, 66, 67 (lanes 0..3)
     T hF[9], p0v, h0v = T(0);
     if constexpr (PX) {
-        pull9_cols(fin, cb, sy, nx, ny, py, N, fL);
+        pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, nx, ny, py, N, fL);
         p0v = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
         if (lane < 4) {
-            pull9_cols(fin, hb, sy, nx, ny, py, N, hF);
+            pull9_cols<T, (NT & 2) != 0>(fin, hb, sy, nx, ny, py, N, hF);
             h0v = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
         }
     } else {
@@ -391,7 +402,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     T gpl[9];
     T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
     if (do_update) {
-        if constexpr (PX) pull9_cols(gpc<T>(d.g[cur]), cb, yu, nx, ny, py, N, gpl);
+        if constexpr (PX) pull9_cols<T, (NT & 1) != 0>(gpc<T>(d.g[cur]), cb, yu, nx, ny, py, N, gpl);
         else pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gpl);
         lAx = *at_bytes(gpc<T>(d.lagA) + rowu, cu);
         lAy = *at_bytes(gpc<T>(d.lagA) + (N + rowu), cu);
@@ -487,7 +498,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
 }
 
 // One (domain, strip, chunk) tile of the strip kernel at the given step offset.
-template <typename T, int CH, bool HAS_S, int MODE, bool PX>
+template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT = 0>
 __device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
                                            int step_offset, double* __restrict__ mom_out) {
     const KConst<T> K = kconst<T>(d);
@@ -505,19 +516,19 @@ __device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S
     // (the row loaded two iterations earlier)
     constexpr int R = CH + 4;
     for (int r = 0; r < R; r += 3) {
-        strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r, x0, y0, lane, cur, dS, cb, hb, F0, F1, mom_out);
+        strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r, x0, y0, lane, cur, dS, cb, hb, F0, F1, mom_out);
         if (r + 1 < R)
-            strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r + 1, x0, y0, lane, cur, dS, cb, hb, F1, F2, mom_out);
+            strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r + 1, x0, y0, lane, cur, dS, cb, hb, F1, F2, mom_out);
         if (r + 2 < R)
-            strip_iter<T, CH, HAS_S, MODE, PX>(d, K, sh, r + 2, x0, y0, lane, cur, dS, cb, hb, F2, F0, mom_out);
+            strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r + 2, x0, y0, lane, cur, dS, cb, hb, F2, F0, mom_out);
     }
 }
 
-template <typename T, int CH, bool HAS_S, int MODE>
+template <typename T, int CH, bool HAS_S, int MODE, int NT = 0>
 __device__ __forceinline__ void strip_tile(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
                                            int step_offset, double* __restrict__ mom_out) {
-    if (d.px) strip_rows<T, CH, HAS_S, MODE, true>(d, sh, x0, y0, step_offset, mom_out);
-    else strip_rows<T, CH, HAS_S, MODE, false>(d, sh, x0, y0, step_offset, mom_out);
+    if (d.px) strip_rows<T, CH, HAS_S, MODE, true, NT>(d, sh, x0, y0, step_offset, mom_out);
+    else strip_rows<T, CH, HAS_S, MODE, false, NT>(d, sh, x0, y0, step_offset, mom_out);
 }
 
 template <typename T, int CH, bool HAS_S, int MODE>
@@ -608,7 +619,7 @@ strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, in
 // workgroup barriers, so the NW strips advance row by row in lockstep and the
 // columns that neighbouring strips share (their stencil and pull halos) are
 // read while the other strip's wavefront holds the same cache lines.
-template <typename T, int CH, bool HAS_S, int MODE, int NW>
+template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT>
 __device__ __forceinline__ void strip_group_body(StripShared<T, HAS_S>* sh, const DomDev* __restrict__ doms,
                                                  const int4* __restrict__ tiles, int ntiles, int step_offset,
                                                  double* __restrict__ mom_out) {
@@ -629,7 +640,7 @@ __device__ __forceinline__ void strip_group_body(StripShared<T, HAS_S>* sh, cons
         }
         return;
     }
-    strip_tile<T, CH, HAS_S, MODE>(d, sh[w], x0, tile.z, step_offset, mom_out);
+    strip_tile<T, CH, HAS_S, MODE, NT>(d, sh[w], x0, tile.z, step_offset, mom_out);
 }
 
 // Compiled for four wavefronts per SIMD (at most 128 VGPRs): the FP32 step
@@ -640,19 +651,20 @@ strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ til
                    int step_offset, double* __restrict__ mom_out) {
     static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
     __shared__ StripShared<T, HAS_S> sh[NW];
-    strip_group_body<T, CH, HAS_S, MODE, NW>(sh, doms, tiles, ntiles, step_offset, mom_out);
+    strip_group_body<T, CH, HAS_S, MODE, NW, 0>(sh, doms, tiles, ntiles, step_offset, mom_out);
 }
 
 // The same groups with the register budget left to the compiler (the FP64
 // step takes about 230 VGPRs, two wavefronts per SIMD), so the FP64 build
-// gets the shared halos without spilling.
-template <typename T, int CH, bool HAS_S, int MODE, int NW>
+// gets the shared halos without spilling.  NT selects non-temporal loads of
+// the pulled populations: bit 0 the NS lattice g, bit 1 the CH lattice f.
+template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT>
 __global__ void __launch_bounds__(64 * NW)
 strip_group_kernel_wide(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
                         int step_offset, double* __restrict__ mom_out) {
     static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
     __shared__ StripShared<T, HAS_S> sh[NW];
-    strip_group_body<T, CH, HAS_S, MODE, NW>(sh, doms, tiles, ntiles, step_offset, mom_out);
+    strip_group_body<T, CH, HAS_S, MODE, NW, NT>(sh, doms, tiles, ntiles, step_offset, mom_out);
 }
 
 // Same kernel compiled for five wavefronts per SIMD (fewer registers, a few

@@ -66,7 +66,7 @@ def test_fp64_parity(orc, name, factory, steps):
 def test_every_tile_shape_consistent(orc):
     """The tile shape changes only the work decomposition: shapes served by the
     same kernel source agree bit for bit (the strip kernel alone or in
-    lockstep groups, codes 8-11 and 17-22); the tile (codes 1-7), strip,
+    lockstep groups, codes 8-11 and 17-24); the tile (codes 1-7), strip,
     pipelined strip (12-14) and five-waves strip (15-16) kernels may contract
     multiply-adds differently, so across them the results agree to rounding
     (FP32: 2e-6 of the largest population after 40 steps; FP64: 1e-13)."""
@@ -102,7 +102,7 @@ def test_group_codes_on_a_batch_of_ragged_domains():
     wavefronts of the missing strips meeting the barriers only.  A batch of
     domains of 5, 3, 9 and 9 strips (groups of 4 and 2 with one to three
     missing strips; periodic and walled; with and without S; ragged in y)
-    stepped under codes 17, 18 and 20-22 equals the single-strip code 9 bit
+    stepped under codes 17, 18 and 20-24 equals the single-strip code 9 bit
     for bit, in both precisions."""
     specs = [G.solid_disk_box(n=300, ny=40, Rs=9.0, R0=11.0, periodic_y=0, rho=(1.0, 1.0, 0.1),
                               mu=(0.15, 0.15, 0.015)),
@@ -112,7 +112,7 @@ def test_group_codes_on_a_batch_of_ragged_domains():
              G.solid_disk_box(n=520, ny=35, Rs=8.0, R0=9.0, periodic_y=0)]
     for prec in (32, 64):
         ref = None
-        for code in (9, 17, 18, 20, 21, 22):
+        for code in (9, 17, 18, 20, 21, 22, 23, 24):
             _say("group batch", code, prec)
             ctx = gpu_context(specs, precision=prec, tile=code)
             ctx.step(30)
