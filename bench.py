@@ -88,6 +88,8 @@ def main():
                     help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy-ceiling", dest="copy_ceiling", action="store_false",
+                    help="skip the 1 GiB device copy that measures the achievable HBM bandwidth")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain device copy run once before the steps; its "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM traffic figures")
@@ -107,6 +109,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    copy_gbs = None
+    if args.copy_ceiling:
+        # achievable HBM bandwidth: the library's non-temporal device copy
+        from paper_2311_05091_amd.lbm import copy_bandwidth
+        copy_gbs = copy_bandwidth(1 << 30, nontemporal=True) / 1e9
+        print("[bench] device copy (1 GiB, non-temporal): %.1f GB/s" % copy_gbs, flush=True)
 
     specs, wname = workload(args.workload, args.nx, args.ny)
     nodes = sum(s.nx * s.ny for s in specs)
@@ -144,6 +153,9 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if args.launch_mode else PMC_TRAFFIC_BYTES.get((code, args.precision, wname)),
             "bytes_per_node": bpn, "kernel_ms": round(kern_ms, 5)}
+    if copy_gbs:
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),

@@ -172,6 +172,18 @@ int tpf_derived(tpf_ctx* ctx, int32_t id, double* k, double* gamma3, double* gam
  * the last call, measured with HIP events on the context's stream. */
 int tpf_kernel_timing(tpf_ctx* ctx, int32_t enable, double* avg_ms, int64_t* launches);
 
+/* Roofline context, not part of the method: device-to-device copy of `bytes`
+ * bytes from src to dst (caller-owned device buffers, 16-byte aligned, bytes
+ * a positive multiple of 16, not overlapping) with 16-byte vector loads and
+ * stores, plain (nontemporal = 0) or with the non-temporal hint (1), as a
+ * grid-stride loop over 65536 workgroups of 256 threads; two untimed copies,
+ * then `reps` copies timed with HIP events on hip_stream (NULL: the null
+ * stream).  *ms_per_copy receives the mean duration of one copy; it moves
+ * 2 * bytes of HBM traffic.  TPF_EINVAL for bad arguments, TPF_EDEVICE for a
+ * HIP error. */
+int tpf_copy_bandwidth(const void* src, void* dst, uint64_t bytes, int32_t nontemporal, int32_t reps,
+                       void* hip_stream, double* ms_per_copy);
+
 const char* tpf_strerror(int32_t status);
 void tpf_destroy(tpf_ctx* ctx);
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1021,6 +1022,53 @@ extern "C" int tpf_kernel_timing(tpf_ctx* c, int32_t enable, double* avg_ms, int
     if (avg_ms) *avg_ms = n ? acc / n : 0.0;
     if (launches) *launches = n;
     c->timing = enable != 0;
+    return TPF_OK;
+}
+
+// Device copy used as the achievable-bandwidth reference of the roofline.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+static __global__ void __launch_bounds__(256) copy16_k(const v4f* __restrict__ a, v4f* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        if constexpr (NT) __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+        else b[i] = a[i];
+    }
+}
+
+extern "C" int tpf_copy_bandwidth(const void* src, void* dst, uint64_t bytes, int32_t nontemporal, int32_t reps,
+                                  void* hip_stream, double* ms_per_copy) {
+    if (!src || !dst || !ms_per_copy || bytes == 0 || bytes % 16 || reps < 1 || (nontemporal != 0 && nontemporal != 1))
+        return TPF_EINVAL;
+    if ((uintptr_t)src % 16 || (uintptr_t)dst % 16) return TPF_EINVAL;
+    const char* s0 = (const char*)src;
+    const char* d0 = (const char*)dst;
+    if (s0 < d0 + bytes && d0 < s0 + bytes) return TPF_EINVAL;
+    const size_t n = bytes / 16;
+    const unsigned grid = (unsigned)std::min<size_t>(65536, (n + 255) / 256);
+    hipStream_t st = (hipStream_t)hip_stream;
+    auto launch = [&]() {
+        if (nontemporal)
+            hipLaunchKernelGGL(copy16_k<true>, dim3(grid), dim3(256), 0, st, (const v4f*)src, (v4f*)dst, n);
+        else
+            hipLaunchKernelGGL(copy16_k<false>, dim3(grid), dim3(256), 0, st, (const v4f*)src, (v4f*)dst, n);
+    };
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    launch();
+    launch();
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(a, st));
+    for (int r = 0; r < reps; ++r) launch();
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(b, st));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_per_copy = ms / reps;
     return TPF_OK;
 }
 

@@ -98,6 +98,7 @@ def library() -> C.CDLL:
         "tpf_domain_size": (C.c_int, [V, C.c_int32, _I32, _I32]),
         "tpf_derived": (C.c_int, [V, C.c_int32, _D, _D, _D, _D]),
         "tpf_kernel_timing": (C.c_int, [V, C.c_int32, _D, _I64]),
+        "tpf_copy_bandwidth": (C.c_int, [V, V, C.c_uint64, C.c_int32, C.c_int32, V, _D]),
         "tpf_strerror": (C.c_char_p, [C.c_int32]),
         "tpf_destroy": (None, [V]),
     }
@@ -114,7 +115,23 @@ EXPORTED = ("tpf_default_params", "tpf_create", "tpf_add_domain", "tpf_arena_byt
             "tpf_get_populations", "tpf_save", "tpf_load", "tpf_set_tile", "tpf_get_tile",
             "tpf_tile_codes", "tpf_autotune", "tpf_set_launch_mode", "tpf_bytes_per_node",
             "tpf_num_domains", "tpf_domain_size", "tpf_derived", "tpf_kernel_timing",
-            "tpf_strerror", "tpf_destroy")
+            "tpf_copy_bandwidth", "tpf_strerror", "tpf_destroy")
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, nontemporal: bool = True, reps: int = 20) -> float:
+    """HBM bandwidth (bytes read + written per second) of the library's device
+    copy of nbytes between two torch device buffers (tpf_copy_bandwidth)."""
+    import torch
+    lib = library()
+    a = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    ms = C.c_double()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(lib.tpf_copy_bandwidth(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nbytes,
+                                  1 if nontemporal else 0, reps, stream, C.byref(ms)), "tpf_copy_bandwidth")
+    if not torch.equal(a, b):
+        raise RuntimeError("tpf_copy_bandwidth: copy mismatch")
+    return 2.0 * nbytes / (ms.value * 1e-3)
 
 
 def strerror(status: int) -> str:

@@ -48,3 +48,18 @@ def test_default_params_are_stable_reading():
     lib.tpf_default_params(ctypes.byref(p), 128, 64)
     assert (p.nx, p.ny, p.periodic_x, p.periodic_y) == (128, 64, 1, 0)
     assert p.d0 == 0.5 and p.tau_phi == 0.8 and p.M_deg == 0.01 and p.rho_gauge == 0.0
+
+
+def test_copy_bandwidth_rejects_bad_arguments_before_any_device_work():
+    lib = _lib("libtpf.so")
+    ms = ctypes.c_double()
+    f = lib.tpf_copy_bandwidth
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    EINVAL = -1
+    assert f(None, None, 16, 0, 1, None, ctypes.byref(ms)) == EINVAL           # null buffers
+    assert f(16, 4096, 10, 0, 1, None, ctypes.byref(ms)) == EINVAL             # size not a multiple of 16
+    assert f(16, 4096, 32, 2, 1, None, ctypes.byref(ms)) == EINVAL             # unknown mode
+    assert f(16, 4096, 32, 0, 0, None, ctypes.byref(ms)) == EINVAL             # no repetition
+    assert f(24, 4096, 32, 0, 1, None, ctypes.byref(ms)) == EINVAL             # misaligned source
+    assert f(16, 32, 32, 0, 1, None, ctypes.byref(ms)) == EINVAL               # overlapping buffers

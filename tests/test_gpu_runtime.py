@@ -208,6 +208,16 @@ def test_invalid_parameters_rejected():
     ctx.close()
 
 
+@pytest.mark.parametrize("nontemporal", [False, True])
+def test_copy_bandwidth_copies_and_times(nontemporal):
+    """The roofline's reference copy moves the data unchanged (checked inside
+    copy_bandwidth) at a plausible HBM rate."""
+    from paper_2311_05091_amd.lbm import copy_bandwidth
+    _say("copy", nontemporal)
+    bw = copy_bandwidth(64 << 20, nontemporal=nontemporal, reps=5)
+    assert 1e11 < bw < 2e13, bw
+
+
 def test_zero_steps_is_noop():
     sp = G.solid_disk_box(n=20)
     ctx = gpu_context([sp], precision=64)
