@@ -102,8 +102,9 @@ int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* d
 
 /* Mass projection of a predicted phase field (the warm start): phi1_out[i] =
  * sigmoid(logit(p_i) + c) (1 - phi0_i) with p_i = pred[i] clipped to
- * [1e-7, 1 - 1e-7] and the shift c in [-40, 40] found by bisection so that
- * sum(phi1_out) = target; a last factor target/sum (|factor - 1| ~ 1e-7) makes
+ * [1e-7, 1 - 1e-7] and the shift c in [-40, 40] such that sum(phi1_out) =
+ * target (the sum increases with c; Newton steps kept inside a bisection
+ * bracket find the root); a last factor target/sum (|factor - 1| ~ 1e-7) makes
  * the sum exact in FP64.  Unlike a multiplicative rescale the field stays in
  * [0, 1 - phi0], so phi2 = 1 - phi0 - phi1 stays non-negative.  pred, phi0:
  * [n] FP32 device; phi1_out: [n] FP64 device; info: 2 FP64 device values
@@ -111,6 +112,14 @@ int tpfnn_resample(const float* src, int32_t N, int32_t sh, int32_t sw, float* d
  * target is out of reach.  One block; deterministic. */
 int tpfnn_mass_project(const float* pred, const float* phi0, int64_t n, double target, double* phi1_out,
                        double* info, void* stream);
+/* The same projection for `count` fields of n nodes each, one block per field,
+ * all launched at once: pred, phi0 [count][n] FP32 device; targets [count]
+ * FP64 device (each positive and finite, else that field's info is NaN as
+ * for an unreachable target); phi1_out [count][n] FP64 device; info
+ * [count][2] FP64 device.  Field b's output equals tpfnn_mass_project on
+ * field b alone. */
+int tpfnn_mass_project_batch(const float* pred, const float* phi0, int32_t count, int64_t n,
+                             const double* targets, double* phi1_out, double* info, void* stream);
 
 /* Network input from physical fields: x[n,h,w,:] = (phi0, (theta - 90 deg)/60 deg,
  * volume scale, plain initial phi1, 0, ..., 0) padded to 32 channels (bf16).

@@ -52,6 +52,7 @@ struct HostDomain {
     DomDev dev;               // host copy of the device descriptor
     int64_t steps = 0;
     int32_t status = TPF_OK;  // TPF_OK, TPF_ENAN, or 1 = retired (residual)
+    bool active = true;       // false: left out of every step until set active again
     double mass = NAN, residual = NAN, snap_norm = NAN;
     int64_t snap_step = -1;
     double k = 0, gamma[3] = {0, 0, 0}, gammaT = 0, eta = 0;
@@ -102,6 +103,9 @@ struct tpf_ctx {
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// A domain takes part in the steps while it is finite, not retired and active.
+static bool stepping(const HostDomain& h) { return h.status == TPF_OK && h.active; }
 
 static const TileShape* find_tile(int code) {
     for (int i = 0; i < kNumTiles; ++i)
@@ -356,7 +360,7 @@ static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<in
 static int refresh_live(tpf_ctx* c) {
     std::vector<int> live;
     for (size_t i = 0; i < c->doms.size(); ++i)
-        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+        if (stepping(c->doms[i])) live.push_back((int)i);
     if (live != c->live_list || c->tiles_dirty || c->tiles_code_built != c->tile_code) {
         c->live_list = live;
         int rc = build_tiles(c, live, c->tiles, &c->tiles_noS);
@@ -432,7 +436,7 @@ static void adapt_tile(tpf_ctx* c) {
     static const int kLadder[] = {17, 9, 8, 2, 1};
     std::vector<int> live;
     for (size_t i = 0; i < c->doms.size(); ++i)
-        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+        if (stepping(c->doms[i])) live.push_back((int)i);
     const int64_t slots = (int64_t)16 * std::max(c->n_cu, 1);
     int pick = kLadder[sizeof(kLadder) / sizeof(kLadder[0]) - 1];
     for (int code : kLadder) {
@@ -460,7 +464,7 @@ static int run_steps(tpf_ctx* c, int64_t n) {
         c->doms[di].dev.live = 1;
     }
     for (size_t i = 0; i < c->doms.size(); ++i)
-        if (c->doms[i].status != TPF_OK) c->doms[i].dev.live = 0;
+        if (!stepping(c->doms[i])) c->doms[i].dev.live = 0;
     rc = upload_descriptors(c);
     if (rc) return rc;
     if (persistent_ok(c)) return run_persistent(c, n);
@@ -692,7 +696,7 @@ extern "C" int tpf_run_to_residual(tpf_ctx* c, double tol, int32_t check_every, 
     for (size_t i = 0; i < c->doms.size(); ++i) start[i] = c->doms[i].steps;
     std::vector<int> live;
     for (size_t i = 0; i < c->doms.size(); ++i)
-        if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+        if (stepping(c->doms[i])) live.push_back((int)i);
     int rc = reduce(c, live, true);  // snapshot at entry
     if (rc) return rc;
     int64_t done = 0;
@@ -700,7 +704,7 @@ extern "C" int tpf_run_to_residual(tpf_ctx* c, double tol, int32_t check_every, 
     while (true) {
         live.clear();
         for (size_t i = 0; i < c->doms.size(); ++i)
-            if (c->doms[i].status == TPF_OK) live.push_back((int)i);
+            if (stepping(c->doms[i])) live.push_back((int)i);
         if (live.empty()) break;
         if (done >= max_steps) {
             budget = true;
@@ -764,6 +768,14 @@ extern "C" int tpf_read_diag(tpf_ctx* c, int32_t id, double* mass, double* resid
     if (residual) *residual = h.residual;
     if (status) *status = h.status;
     if (steps) *steps = h.steps;
+    return TPF_OK;
+}
+
+extern "C" int tpf_set_active(tpf_ctx* c, int32_t id, int32_t active) {
+    if (!c || id < 0 || id >= (int)c->doms.size() || (active != 0 && active != 1)) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    c->doms[id].active = active != 0;
+    c->tiles_dirty = true;
     return TPF_OK;
 }
 

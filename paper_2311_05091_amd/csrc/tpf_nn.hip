@@ -618,9 +618,11 @@ __global__ void resample_k(const float* __restrict__ src, int N, int sh, int sw,
 }
 
 // Mass projection of a predicted phase field by a shift of its logit:
-// phi1 = sigmoid(logit(p) + c) (1 - phi0), with c found by bisection so that
-// sum(phi1) equals the target (the sum is increasing in c).  One block; FP32
-// sigmoid, FP64 sums in a fixed order, so the result is deterministic.
+// phi1 = sigmoid(logit(p) + c) (1 - phi0), with the c that gives
+// sum(phi1) = the target (the sum is increasing in c): Newton steps on the
+// sum, kept inside a bisection bracket (a step that would leave it bisects
+// instead).  One block; FP32 sigmoid, FP64 sums in a fixed order, so the
+// result is deterministic.
 constexpr int kProjThreads = 1024;
 constexpr float kProjClip = 1e-7f;
 constexpr float kProjRange = 40.f;
@@ -641,37 +643,60 @@ __device__ double block_sum_1024(double v, double* red) {
     return t;
 }
 
+// Block b projects field b of a batch of equal-size fields: pred, phi0 and
+// out advance by n per field, info by 2; its mass is targets[b] (target0
+// when targets is null, a single field).
 __global__ void __launch_bounds__(kProjThreads)
-mass_project_k(const float* __restrict__ pred, const float* __restrict__ phi0, int64_t n, double target,
-               double* __restrict__ out, double* __restrict__ info) {
+mass_project_k(const float* __restrict__ pred_all, const float* __restrict__ phi0_all, int64_t n,
+               const double* __restrict__ targets, double target0, double* __restrict__ out_all,
+               double* __restrict__ info_all) {
     __shared__ double red[kProjThreads / 64];
-    auto mass = [&](float c) {
-        double acc = 0.0;
+    const int64_t b = blockIdx.x;
+    const float* __restrict__ pred = pred_all + b * n;
+    const float* __restrict__ phi0 = phi0_all + b * n;
+    double* __restrict__ out = out_all + b * n;
+    double* __restrict__ info = info_all + 2 * b;
+    const double target = targets ? targets[b] : target0;
+    // sum of phi1 at shift c and its derivative in c
+    auto mass = [&](float c, double* dmass) {
+        double acc = 0.0, dacc = 0.0;
         for (int64_t i = threadIdx.x; i < n; i += kProjThreads) {
             const float z = proj_logit(pred[i]) + c;
-            acc += (double)((1.f - phi0[i]) / (1.f + __expf(-z)));
+            const float sg = 1.f / (1.f + __expf(-z));
+            const float w = 1.f - phi0[i];
+            acc += (double)(w * sg);
+            if (dmass) dacc += (double)(w * sg * (1.f - sg));
         }
-        return block_sum_1024(acc, red);
+        const double m = block_sum_1024(acc, red);
+        if (dmass) *dmass = block_sum_1024(dacc, red);
+        return m;
     };
-    const double m_lo = mass(-kProjRange), m_hi = mass(kProjRange);
+    const double m_lo = mass(-kProjRange, nullptr), m_hi = mass(kProjRange, nullptr);
     if (!(target > m_lo && target < m_hi)) {
         for (int64_t i = threadIdx.x; i < n; i += kProjThreads) out[i] = 0.0;
         if (threadIdx.x == 0) info[0] = info[1] = __builtin_nan("");
         return;
     }
-    float lo = -kProjRange, hi = kProjRange;
-    for (int it = 0; it < 48 && lo < hi; ++it) {
-        const float c = 0.5f * (lo + hi);
-        if (c == lo || c == hi) break;
-        if (mass(c) < target) lo = c;
+    float lo = -kProjRange, hi = kProjRange, c = 0.f;
+    for (int it = 0; it < 48; ++it) {
+        double dm = 0.0;
+        const double m = mass(c, &dm);
+        if (fabs(m - target) <= 1e-9 * target) break;
+        if (m < target) lo = c;
         else hi = c;
+        float cn = (float)((double)c + (target - m) / dm);
+        if (!(dm > 0.0) || !(cn > lo && cn < hi)) cn = 0.5f * (lo + hi);
+        if (cn == c || lo >= hi) break;
+        c = cn;
     }
-    const float c = 0.5f * (lo + hi);
-    const double m = mass(c);
-    const double scale = target / m;  // removes the last bisection residue (|scale - 1| ~ 1e-7)
+    const double m = mass(c, nullptr);
+    const double scale = target / m;  // removes the last residue of the root search
     for (int64_t i = threadIdx.x; i < n; i += kProjThreads) {
+        // the same FP32 expression as in mass(), so that the FP64 sum of the
+        // output is target to rounding
         const float z = proj_logit(pred[i]) + c;
-        out[i] = (double)((1.f - phi0[i]) / (1.f + __expf(-z))) * scale;
+        const float sg = 1.f / (1.f + __expf(-z));
+        out[i] = (double)((1.f - phi0[i]) * sg) * scale;
     }
     if (threadIdx.x == 0) {
         info[0] = c;
@@ -964,8 +989,16 @@ extern "C" int tpfnn_mass_project(const float* pred, const float* phi0, int64_t 
                                   double* phi1_out, double* info, void* stream) {
     if (!pred || !phi0 || !phi1_out || !info || n <= 0 || !(target > 0.0) || !std::isfinite(target))
         return kEinval;
-    hipLaunchKernelGGL(mass_project_k, dim3(1), dim3(kProjThreads), 0, (hipStream_t)stream, pred, phi0, n, target,
-                       phi1_out, info);
+    hipLaunchKernelGGL(mass_project_k, dim3(1), dim3(kProjThreads), 0, (hipStream_t)stream, pred, phi0, n,
+                       (const double*)nullptr, target, phi1_out, info);
+    return launch_status();
+}
+
+extern "C" int tpfnn_mass_project_batch(const float* pred, const float* phi0, int32_t count, int64_t n,
+                                        const double* targets, double* phi1_out, double* info, void* stream) {
+    if (!pred || !phi0 || !targets || !phi1_out || !info || count <= 0 || n <= 0) return kEinval;
+    hipLaunchKernelGGL(mass_project_k, dim3(count), dim3(kProjThreads), 0, (hipStream_t)stream, pred, phi0, n,
+                       targets, 0.0, phi1_out, info);
     return launch_status();
 }
 

@@ -85,6 +85,7 @@ def library() -> C.CDLL:
         "tpf_read_moments": (C.c_int, [V, C.c_int32, _D, _D, _D, _D]),
         "tpf_read_diag": (C.c_int, [V, C.c_int32, _D, _D, _I32, _I64]),
         "tpf_set_phi1": (C.c_int, [V, C.c_int32, _D]),
+        "tpf_set_active": (C.c_int, [V, C.c_int32, C.c_int32]),
         "tpf_get_populations": (C.c_int, [V, C.c_int32, _D, _D]),
         "tpf_save": (C.c_int, [V, C.c_char_p]),
         "tpf_load": (C.c_int, [V, C.c_char_p]),
@@ -111,7 +112,7 @@ def library() -> C.CDLL:
 
 
 EXPORTED = ("tpf_default_params", "tpf_create", "tpf_add_domain", "tpf_arena_bytes", "tpf_finalize",
-            "tpf_step", "tpf_run_to_residual", "tpf_read_moments", "tpf_read_diag", "tpf_set_phi1",
+            "tpf_step", "tpf_run_to_residual", "tpf_read_moments", "tpf_read_diag", "tpf_set_phi1", "tpf_set_active",
             "tpf_get_populations", "tpf_save", "tpf_load", "tpf_set_tile", "tpf_get_tile",
             "tpf_tile_codes", "tpf_autotune", "tpf_set_launch_mode", "tpf_bytes_per_node",
             "tpf_num_domains", "tpf_domain_size", "tpf_derived", "tpf_kernel_timing",
@@ -259,6 +260,10 @@ class Context:
         g = np.empty((9, s.ny, s.nx))
         _check(self.lib.tpf_get_populations(self._h, did, _dptr(f), _dptr(g)), "tpf_get_populations")
         return f, g
+
+    def set_active(self, did: int, active: bool):
+        """Leaves the domain out of (False) or back in (True) the following steps."""
+        _check(self.lib.tpf_set_active(self._h, int(did), 1 if active else 0), "tpf_set_active")
 
     def set_phi1(self, did: int, phi1: np.ndarray):
         a = np.ascontiguousarray(phi1, dtype=np.float64)

@@ -20,7 +20,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -67,6 +67,7 @@ def nnlib() -> C.CDLL:
         "tpfnn_resample": [V, I32, I32, I32, V, I32, I32, V],
         "tpfnn_pack_input": [V, V, V, V, I32, I32, I32, V, V],
         "tpfnn_mass_project": [V, V, I64, C.c_double, V, V, V],
+        "tpfnn_mass_project_batch": [V, V, C.c_int32, I64, V, V, V, V],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -85,7 +86,8 @@ EXPORTED_NN = ("tpfnn_mfma_selftest", "tpfnn_conv3x3_fwd", "tpfnn_weight_flip", 
                "tpfnn_conv3x3_wgrad", "tpfnn_relu_bwd", "tpfnn_avgpool2_fwd", "tpfnn_avgpool2_bwd",
                "tpfnn_upsample2_fwd", "tpfnn_upsample2_bwd", "tpfnn_concat", "tpfnn_split",
                "tpfnn_add_inplace", "tpfnn_head_workspace", "tpfnn_head", "tpfnn_adam", "tpfnn_to_bf16",
-               "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input", "tpfnn_mass_project")
+               "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input", "tpfnn_mass_project",
+               "tpfnn_mass_project_batch")
 
 
 def _ck(rc, what):
@@ -342,9 +344,14 @@ class UNet:
 
     def predict(self, phi0, theta_deg, vol, phi1_init=None) -> np.ndarray:
         """[N,256,256] prediction of phi1 (numpy float32)."""
+        return self.predict_device(phi0, theta_deg, vol, phi1_init).cpu().numpy()
+
+    def predict_device(self, phi0, theta_deg, vol, phi1_init=None):
+        """[N,256,256] prediction of phi1 left on the device: a view of the
+        network's output buffer, valid until its next forward pass (work
+        queued on the same stream before that pass reads it in order)."""
         N = self.pack(phi0, theta_deg, vol, phi1_init)
-        pred = self.forward(N)
-        return pred.reshape(N, RES, RES).cpu().numpy()
+        return self.forward(N).reshape(N, RES, RES)
 
 
 # ---------------------------------------------------------------------------
@@ -390,6 +397,63 @@ def warm_start_field(pred256: np.ndarray, phi0: np.ndarray, target_mass: float, 
     if not np.isfinite(c).all():
         raise ValueError("droplet mass out of reach of the prediction")
     return out.cpu().numpy().reshape(ny, nx)
+
+
+def warm_start_fields(pred, phi0s: Sequence[np.ndarray], targets: Sequence[float]) -> List[Optional[np.ndarray]]:
+    """warm_start_field for a batch of predictions already on the device
+    ([N,256,256] FP32 tensor): resampling (skipped for 256 x 256 domains, where
+    the corner-aligned map is the identity) and mass projection are queued for
+    all N on the current stream and the fields come back in one transfer.
+    None where the prediction is not finite or the mass is out of its reach."""
+    import torch
+    lib = nnlib()
+    N = pred.shape[0]
+    dev = pred.device
+    st = V(torch.cuda.current_stream(dev).cuda_stream)
+    flat = pred.reshape(N, RES * RES)
+    finite = torch.isfinite(flat).all(dim=1).cpu().numpy()
+    sizes = [f.shape for f in phi0s]
+    offs = np.concatenate([[0], np.cumsum([h * w for h, w in sizes])])
+    out = torch.zeros(int(offs[-1]), dtype=torch.float64, device=dev)
+    info = torch.full((N, 2), float("nan"), dtype=torch.float64, device=dev)
+    keep = []
+    if all(sz == sizes[0] for sz in sizes):
+        # equal sizes: one batched resampling (if needed) and one projection launch
+        ny, nx = sizes[0]
+        n = ny * nx
+        if (ny, nx) != (RES, RES):
+            p = torch.empty(N * n, dtype=torch.float32, device=dev)
+            _ck(lib.tpfnn_resample(_p(flat), N, RES, RES, _p(p), ny, nx, st), "resample")
+        else:
+            p = flat
+        t0 = torch.tensor(np.ascontiguousarray(np.stack(phi0s), np.float32), device=dev)
+        tg = torch.tensor(np.where(finite, np.asarray(targets, np.float64), np.nan), device=dev)
+        _ck(lib.tpfnn_mass_project_batch(_p(p), _p(t0), N, n, _p(tg), _p(out), _p(info), st), "mass_project_batch")
+        keep.append((p, t0, tg))
+    else:
+        for d in range(N):
+            if not finite[d]:
+                continue
+            ny, nx = sizes[d]
+            n = ny * nx
+            src = flat[d]
+            if (ny, nx) != (RES, RES):
+                p = torch.empty(n, dtype=torch.float32, device=dev)
+                _ck(lib.tpfnn_resample(_p(src), 1, RES, RES, _p(p), ny, nx, st), "resample")
+            else:
+                p = src
+            t0 = torch.tensor(np.ascontiguousarray(phi0s[d], np.float32).ravel(), device=dev)
+            _ck(lib.tpfnn_mass_project(_p(p), _p(t0), n, float(targets[d]), _p(out[int(offs[d]):]), _p(info[d]),
+                                       st), "mass_project")
+            keep.append((p, t0))  # alive until the queued kernels ran
+    fields = out.cpu().numpy()
+    infos = info.cpu().numpy()
+    del keep
+    res: List[Optional[np.ndarray]] = []
+    for d in range(N):
+        ok = finite[d] and np.isfinite(infos[d]).all()
+        res.append(fields[int(offs[d]):int(offs[d + 1])].reshape(sizes[d]).copy() if ok else None)
+    return res
 
 
 def main(argv=None):

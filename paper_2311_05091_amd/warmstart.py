@@ -104,20 +104,25 @@ def build_dataset(specs: List[G.DomainSpec], phi_eq: List[np.ndarray], status) -
 def predict_fields(net: S.UNet, specs: List[G.DomainSpec], batch: int = 32):
     """Warm-start fields (mass-projected, on each domain's grid) for the
     domains; None where the prediction is unusable."""
-    preds = []
+    def to_res(fields):
+        # one resampling call per group of equal-size domains; a field already
+        # at the network's resolution is kept as it is (the corner-aligned
+        # bilinear map is then the identity)
+        shape = fields[0].shape
+        if all(f.shape == shape for f in fields):
+            a = np.stack(fields).astype(np.float32)
+            return a if shape == (S.RES, S.RES) else S.resample(a, S.RES, S.RES)
+        return np.stack([S.resample(f[None], S.RES, S.RES)[0] for f in fields])
+
+    fields = []
     for b0 in range(0, len(specs), batch):
         grp = specs[b0:b0 + batch]
-        phi0 = np.stack([S.resample(sp.phi0[None], S.RES, S.RES)[0] for sp in grp])
-        phi1 = np.stack([S.resample(sp.phi1[None], S.RES, S.RES)[0] for sp in grp])
+        phi0 = to_res([sp.phi0 for sp in grp])
+        phi1 = to_res([sp.phi1 for sp in grp])
         th = np.array([sp.theta_deg for sp in grp], np.float32)
         vol = np.array([S.volume_feature(sp.phi1) for sp in grp], np.float32)
-        preds.extend(list(net.predict(phi0, th, vol, phi1)))
-    fields = []
-    for sp, pr in zip(specs, preds):
-        try:
-            fields.append(S.warm_start_field(pr, sp.phi0, float(np.sum(sp.phi1))))
-        except ValueError:
-            fields.append(None)
+        pred = net.predict_device(phi0, th, vol, phi1)
+        fields.extend(S.warm_start_fields(pred, [sp.phi0 for sp in grp], [float(np.sum(sp.phi1)) for sp in grp]))
     return fields
 
 
@@ -178,17 +183,22 @@ def train(data: Dict[str, np.ndarray], epochs: int = 30, batch: int = 8, lr: flo
 
 
 def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: int, max_steps: int,
-             precision: int = 32, launch_mode: int = 2, gate: float = 0.0, log=print) -> Dict:
+             precision: int = 32, launch_mode: int = 2, gate: float = 0.0, probe_steps: int = 0,
+             log=print) -> Dict:
     """Plain vs learned time to r < tol on the same held-out domains, each side
     one batch (converged domains retire).
 
-    Learned side, timed as a whole: inference, mass-projected warm start
-    (kept only where it differs from the plain initial condition by at least
-    ``gate`` in relative L2) and relaxation to the tolerance; a domain that
-    turns non-finite restarts from the plain initial condition afterwards (its
-    wasted steps count against it).  Work is compared as node-steps (each domain's steps x its nodes),
-    which is what the batched GPU time follows once the batch is large; the
-    batch wall times are reported beside it."""
+    Learned side, timed as a whole: an optional probe (all domains relax from
+    the plain initial condition for ``probe_steps`` steps; those that converge
+    within it need no surrogate), then inference for the others, the
+    mass-projected warm start (kept only where it differs from the plain
+    initial condition by at least ``gate`` in relative L2; elsewhere the plain
+    relaxation simply continues) and relaxation to the tolerance.  Steps of
+    the probe count for every domain.  A domain that turns non-finite restarts
+    from the plain initial condition afterwards (its wasted steps count
+    against it).  Work is compared as node-steps (each domain's steps x its
+    nodes), which is what the batched GPU time follows once the batch is
+    large; the batch wall times are reported beside it."""
     plain = sweep(specs, tol, check_every, max_steps, precision=precision, launch_mode=launch_mode)
     log(json.dumps({"plain_wall_s": round(plain["wall_s"], 3), "plain_rc": plain["rc"],
                     "plain_steps_mean": float(np.mean(plain["steps"]))}))
@@ -200,19 +210,34 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
         ctx.set_launch_mode(launch_mode)
     _sync()
     t0 = time.perf_counter()
-    fields = predict_fields(net, specs)
-    empty = sum(f is None for f in fields)
+    n = len(specs)
+    steps = np.zeros(n, dtype=np.int64)
+    todo = list(range(n))
+    if probe_steps > 0:
+        rc1, s1 = ctx.run_to_residual(tol, check_every=check_every, max_steps=probe_steps)
+        steps += s1
+        nan = {i for i in range(n) if rc1 == TPF_ENAN and ctx.diag(i)["status"] == TPF_ENAN}
+        todo = [i for i in range(n) if s1[i] >= probe_steps and i not in nan]
+        for i in range(n):
+            if s1[i] < probe_steps and i not in nan:
+                ctx.set_active(i, False)  # converged within the probe: done
+    t_probe = time.perf_counter() - t0
+    fields: List = [None] * n
+    for i, f in zip(todo, predict_fields(net, [specs[i] for i in todo]) if todo else []):
+        fields[i] = f
+    empty = sum(fields[i] is None for i in todo)
     gated = 0
-    for i, sp in enumerate(specs):
+    for i in todo:
         f = fields[i]
-        if f is not None and rel_l2(f, sp.phi1) < gate:
-            f = None
+        if f is not None and rel_l2(f, specs[i].phi1) < gate:
             gated += 1
-        ctx.set_phi1(i, sp.phi1 if f is None else f)
+        elif f is not None:
+            ctx.set_phi1(i, f)
     _sync()
-    t_inf = time.perf_counter() - t0
-    rc, steps = ctx.run_to_residual(tol, check_every=check_every, max_steps=max_steps)
-    steps = np.asarray(steps, dtype=np.int64).copy()
+    t_inf = time.perf_counter() - t0 - t_probe
+    if todo:
+        _, s2 = ctx.run_to_residual(tol, check_every=check_every, max_steps=max(max_steps - probe_steps, 0))
+        steps += s2
     _sync()
     t_learn = time.perf_counter() - t0
     phi_l = [ctx.moments(i)[0] for i in range(len(specs))]
@@ -242,6 +267,7 @@ def evaluate(net: S.UNet, specs: List[G.DomainSpec], tol: float, check_every: in
     finite_err = [e for e in err if np.isfinite(e)]
     out = {"domains": len(specs), "tol": tol, "check_every": check_every, "cap": max_steps,
            "plain_wall_s": plain["wall_s"], "learned_wall_s": t_learn, "inference_s": t_inf,
+           "probe_steps": probe_steps, "probe_s": t_probe, "probe_converged": n - len(todo),
            "wall_speedup": plain["wall_s"] / t_learn,
            "work_speedup": float((ps[ok] * nodes[ok]).sum() / max((ls[ok] * nodes[ok]).sum(), 1.0)),
            "plain_steps_mean": float(ps.mean()), "learned_steps_mean": float(ls.mean()),
@@ -282,7 +308,7 @@ def main(argv=None):
     import argparse
     import os
     ap = argparse.ArgumentParser(description="batched sweep -> surrogate training -> warm-start evaluation")
-    ap.add_argument("--train-domains", type=int, default=768)
+    ap.add_argument("--train-domains", type=int, default=1536)
     ap.add_argument("--smin", type=int, default=128)
     ap.add_argument("--smax", type=int, default=512)
     ap.add_argument("--eval-domains", type=int, default=256)
@@ -293,13 +319,15 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=250)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=5e-4)
-    ap.add_argument("--train-budget-s", type=float, default=300.0)
+    ap.add_argument("--train-budget-s", type=float, default=420.0)
     ap.add_argument("--sweep-group", type=int, default=64, help="domains per sweep context (logged per group)")
     ap.add_argument("--launch-mode", type=int, default=2,
                     help="0: one launch per step, fixed tiles; 1: persistent; 2: tiles follow the live work")
     ap.add_argument("--gate", type=float, default=-1.0,
                     help="warm-start gate (rel. L2 to the plain start); < 0: calibrated on validation domains")
     ap.add_argument("--weights", default="", help="load trained weights instead of sweeping and training")
+    ap.add_argument("--probe-steps", type=int, default=500,
+                    help="learned side: steps of the plain start before the surrogate is consulted (0: none)")
     ap.add_argument("--out", default="warmstart_out")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
@@ -345,7 +373,7 @@ def main(argv=None):
     held = G.held_out_set(n_domains=args.eval_domains, s=256)
     log(json.dumps({"phase": "evaluate", "domains": len(held)}))
     result["evaluate"] = evaluate(net, held, args.tol, args.check_every, args.eval_cap,
-                                  launch_mode=args.launch_mode, gate=gate, log=log)
+                                  launch_mode=args.launch_mode, gate=gate, probe_steps=args.probe_steps, log=log)
     with open(os.path.join(args.out, "result.json"), "w") as f:
         json.dump(result, f, indent=1, default=float)
     ev = result["evaluate"]

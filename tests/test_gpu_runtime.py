@@ -218,6 +218,34 @@ def test_copy_bandwidth_copies_and_times(nontemporal):
     assert 1e11 < bw < 2e13, bw
 
 
+def test_inactive_domain_is_left_out_and_resumes():
+    """An inactive domain keeps its state through steps and runs to a
+    residual (0 steps counted); the others advance as they would alone; once
+    active again it continues as if it had not been paused."""
+    a = G.solid_disk_box(n=40, ny=24, periodic_y=0)
+    b = G.solid_disk_box(n=67, ny=23, Rs=5.0, R0=6.0, periodic_y=0)
+    _say("set_active")
+    ctx = gpu_context([a, b], precision=64)
+    ref = gpu_context([b], precision=64)
+    ctx.set_active(0, False)
+    fa0 = ctx.populations(0)
+    ctx.step(30)
+    ref.step(30)
+    assert np.array_equal(ctx.populations(0)[0], fa0[0]) and np.array_equal(ctx.populations(0)[1], fa0[1])
+    assert np.array_equal(ctx.populations(1)[0], ref.populations(0)[0])
+    rc, steps = ctx.run_to_residual(1e-30, check_every=10, max_steps=20)
+    assert steps[0] == 0 and steps[1] == 20
+    ctx.set_active(0, True)
+    ctx.step(15)
+    alone = gpu_context([a], precision=64)
+    alone.step(15)
+    assert np.array_equal(ctx.populations(0)[0], alone.populations(0)[0])
+    with pytest.raises(lbm.TpfError):
+        ctx.set_active(5, True)
+    for c in (ctx, ref, alone):
+        c.close()
+
+
 def test_zero_steps_is_noop():
     sp = G.solid_disk_box(n=20)
     ctx = gpu_context([sp], precision=64)

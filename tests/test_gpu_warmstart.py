@@ -46,6 +46,13 @@ def test_warm_start_pipeline_small(tmp_path):
     assert ev["learned_nan"] == 0 and ev["plain_nan"] == 0
     assert all(0 < s <= 4000 for s in pd["plain_steps"]) and all(0 < s <= 8000 for s in pd["learned_steps"])
     assert 0 <= ev["gated_to_plain"] <= 4
+    # with a probe of the plain start first: domains converged within it skip the surrogate
+    ev2 = W.evaluate(net, held, tol=1e-4, check_every=50, max_steps=4000, gate=gate, probe_steps=100,
+                     log=lambda m: None)
+    pd2 = ev2["per_domain"]
+    assert ev2["probe_steps"] == 100 and 0 <= ev2["probe_converged"] <= 4 and ev2["learned_nan"] == 0
+    assert all(0 < s <= 8000 for s in pd2["learned_steps"])
+    assert sum(np.isfinite(pd2["surrogate_rel_l2"])) <= 4 - ev2["probe_converged"]
 
 
 def test_warm_start_field_is_mass_exact_and_bounded():
@@ -70,3 +77,35 @@ def test_warm_start_field_is_mass_exact_and_bounded():
     assert d["status"] != TPF_ENAN
     assert abs(d["mass"] - target) <= 1e-5 * target
     ctx.close()
+
+
+def test_batched_warm_start_fields_equal_single():
+    """The batched device path gives the per-domain warm-start fields bit for
+    bit (same kernels), at the network's resolution and resampled, and None
+    for a non-finite prediction."""
+    import torch
+    from paper_2311_05091_amd import surrogate as S
+    _say("batched warm start fields")
+    specs = [G.held_out_set(n_domains=1, s=256, seed0=902)[0], G.held_out_set(n_domains=1, s=128, seed0=903)[0],
+             G.held_out_set(n_domains=1, s=200, seed0=904)[0]]
+    rng = np.random.default_rng(6)
+    pred = np.clip(0.5 + 0.4 * rng.normal(size=(3, 256, 256)), 0.0, 1.0).astype(np.float32)
+    targets = [float(np.sum(sp.phi1)) for sp in specs]
+    got = S.warm_start_fields(torch.tensor(pred, device="cuda"), [sp.phi0 for sp in specs], targets)
+    for d, sp in enumerate(specs):
+        ref = S.warm_start_field(pred[d], sp.phi0, targets[d])
+        assert got[d] is not None and got[d].shape == ref.shape and np.array_equal(got[d], ref), d
+    pred[1, 5, 5] = np.nan
+    got = S.warm_start_fields(torch.tensor(pred, device="cuda"), [sp.phi0 for sp in specs], targets)
+    assert got[1] is None and got[0] is not None and got[2] is not None
+    # equal sizes take the batched launches (resampled at 128, identity at 256)
+    for s_ in (128, 256):
+        same = G.held_out_set(n_domains=3, s=s_, seed0=910)
+        tg = [float(np.sum(sp.phi1)) for sp in same]
+        pr = np.clip(0.5 + 0.4 * rng.normal(size=(3, 256, 256)), 0.0, 1.0).astype(np.float32)
+        pr[2, 0, 0] = np.inf
+        got = S.warm_start_fields(torch.tensor(pr, device="cuda"), [sp.phi0 for sp in same], tg)
+        assert got[2] is None
+        for d in range(2):
+            ref = S.warm_start_field(pr[d], same[d].phi0, tg[d])
+            assert got[d] is not None and np.array_equal(got[d], ref), (s_, d)
