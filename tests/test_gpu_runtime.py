@@ -256,17 +256,22 @@ def test_zero_steps_is_noop():
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_full_size_porous_workload(orc, prec):
-    """The benchmark workload (4096 x 2048 porous medium) at full size, autotuned
-    tile as in the benchmark: 3 steps against the oracle at every node.
+@pytest.mark.parametrize("prec,tile", [(64, 24), (32, 23), (32, 0)])
+def test_full_size_porous_workload(orc, prec, tile):
+    """The benchmark workload (4096 x 2048 porous medium) at full size, in the
+    tile shapes the benchmark's autotuner takes on it (FP32 23, FP64 24: groups
+    of four 64 x 64 strips with non-temporal loads) and in whatever a short
+    autotune picks (tile 0): 3 steps against the oracle at every node.
     FP64: <= 1e-11 of the field maximum.  FP32: phi within 2e-6 absolute
     (a few FP32 ulps of O(1) populations per step); u and p within 1e-3 of
     their maxima (they come from O(1e-6) differences of FP32 values)."""
     sp = G.porous_medium()
-    _say("full size porous", prec)
+    _say("full size porous", prec, tile)
     ctx = gpu_context([sp], precision=prec)
-    ctx.autotune(steps=3)
+    if tile:
+        ctx.set_tile(tile)
+    else:
+        ctx.autotune(steps=3)
     ctx.step(3)
     g = ctx.moments(0)
     ctx.close()
