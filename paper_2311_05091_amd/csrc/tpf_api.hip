@@ -1066,20 +1066,28 @@ extern "C" int tpf_copy_bandwidth(const void* src, void* dst, uint64_t bytes, in
             hipLaunchKernelGGL(copy16_k<false>, dim3(grid), dim3(256), 0, st, (const v4f*)src, (v4f*)dst, n);
     };
     hipEvent_t a = nullptr, b = nullptr;
-    HIP_OK(hipEventCreate(&a));
-    HIP_OK(hipEventCreate(&b));
-    launch();
-    launch();
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipEventRecord(a, st));
-    for (int r = 0; r < reps; ++r) launch();
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipEventRecord(b, st));
-    HIP_OK(hipEventSynchronize(b));
     float ms = 0;
-    HIP_OK(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) {
+        launch();
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e == hipSuccess) {
+        for (int r = 0; r < reps; ++r) launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "tpf: tpf_copy_bandwidth failed: %s\n", hipGetErrorString(e));
+        return TPF_EDEVICE;
+    }
     *ms_per_copy = ms / reps;
     return TPF_OK;
 }
