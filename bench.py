@@ -36,7 +36,9 @@ METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 # kernel source changes after the counters were taken.
 PMC_TRAFFIC_BYTES = {(23, 32, "porous_displacement_4096x2048"): 1.5229e9,
                      (22, 64, "porous_displacement_4096x2048"): 2.9457e9,
-                     (24, 64, "porous_displacement_4096x2048"): 2.9567e9}
+                     (24, 64, "porous_displacement_4096x2048"): 2.9567e9,
+                     # batched sweep, FP32 tile code 20: 3290843.2 x 1.99974 + 5257530.9 KiB
+                     (20, 32, "batched_sweep_512_domains_60280697_nodes"): 1.2122e10}
 
 
 def workload(name: str, nx: int = 4096, ny: int = 2048):
