@@ -126,7 +126,8 @@ int tpf_set_phi1(tpf_ctx* ctx, int32_t id, const double* phi1);
 /* Leaves domain id out of (active = 0) or back in (1) every following
  * tpf_step and tpf_run_to_residual of the batch: its state stays as it is and
  * its step count in steps_per_domain is 0 while inactive.  Domains are active
- * when added.  TPF_EINVAL for a bad id or value. */
+ * when added; tpf_set_phi1 and tpf_load leave the flag as it is.  TPF_EINVAL
+ * for a bad id or value. */
 int tpf_set_active(tpf_ctx* ctx, int32_t id, int32_t active);
 
 /* Raw state of domain id (post-collision populations f[9][ny][nx],
