@@ -18,7 +18,7 @@
  *     order in which the paper defines it.
  * Lattice units throughout: c = dx = dt = 1.
  *
- * Readings of passages the paper leaves open (each is listed in the design doc):
+ * Readings of passages the paper leaves open:
  *   R1  eta is derived from the CH relaxation time tau_phi = 1/s1 through
  *       (M_cst+M_deg)/gamma_1 = (1/s1 - 1/2) eta c_s^2 (Sec. 3).
  *   R2  gradients and Laplacians use the standard isotropic 9-point central
