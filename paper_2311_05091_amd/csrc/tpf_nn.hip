@@ -59,17 +59,24 @@ __global__ void __launch_bounds__(64) mfma_selftest_k(const uint16_t* A, const u
 // GEMM: M = pixels (64 per block), N = output channels (BN per block),
 // K = 9 * Cin in chunks of 32 channels of one tap.
 // ---------------------------------------------------------------------------
-template <int BN>
+template <int BN, int KC>
 __global__ void __launch_bounds__(256)
 conv3x3_fwd_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint16_t* __restrict__ w,
               const float* __restrict__ bias, int Cout, int relu, uint16_t* __restrict__ y) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[64][40];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][40];
+    // KC input channels staged per barrier pair (32 or 64; Cin a multiple of
+    // KC), row pitch KC + 8 halfwords so that the 16 rows an MFMA operand
+    // reads fall in distinct LDS banks
+    static_assert(KC == 32 || KC == 64, "KC is 32 or 64");
+    constexpr int KP = KC + 8;
+    constexpr int SEGS = KC / 32;   // 16-byte loads per thread and row quarter
+    __shared__ __attribute__((aligned(16))) uint16_t As[64][KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][KP];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int p0 = blockIdx.x * 64;
     const int co0 = blockIdx.y * BN;
     const int HW = H * W;
-    // loader roles
+    // loader roles: thread tid stages row tid / 4 at channel offsets
+    // (tid % 4) * 8 + 32 k, k < SEGS
     const int ar = tid >> 2, aseg = (tid & 3) * 8;
     const int p = p0 + ar;
     const int n = p / HW, rem = p - n * HW;
@@ -86,18 +93,28 @@ conv3x3_fwd_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint1
         const bool inb = (sy >= 0) && (sy < H) && (sx >= 0) && (sx < W);
         const uint16_t* xr = x + ((size_t)(n * H + (inb ? sy : 0)) * W + (inb ? sx : 0)) * Cin;
         const uint16_t* wr = w + ((size_t)bco * 9 + kk) * Cin;
-        for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-            uint4 av = inb ? *(const uint4*)(xr + ci0 + aseg) : make_uint4(0, 0, 0, 0);
-            uint4 bv = bload ? *(const uint4*)(wr + ci0 + bseg) : make_uint4(0, 0, 0, 0);
-            __syncthreads();
-            *(uint4*)&As[ar][aseg] = av;
-            if (bload) *(uint4*)&Bs[tid >> 2][bseg] = bv;
-            __syncthreads();
-            const bf16x8 a = as_bf16x8(*(const uint4*)&As[16 * wave + (lane & 15)][(lane >> 4) * 8]);
+        for (int ci0 = 0; ci0 < Cin; ci0 += KC) {
+            uint4 av[SEGS], bv[SEGS];
 #pragma unroll
-            for (int j = 0; j < BN / 16; ++j) {
-                const bf16x8 b = as_bf16x8(*(const uint4*)&Bs[16 * j + (lane & 15)][(lane >> 4) * 8]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            for (int k = 0; k < SEGS; ++k) {
+                av[k] = inb ? *(const uint4*)(xr + ci0 + aseg + 32 * k) : make_uint4(0, 0, 0, 0);
+                bv[k] = bload ? *(const uint4*)(wr + ci0 + bseg + 32 * k) : make_uint4(0, 0, 0, 0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SEGS; ++k) {
+                *(uint4*)&As[ar][aseg + 32 * k] = av[k];
+                if (bload) *(uint4*)&Bs[tid >> 2][bseg + 32 * k] = bv[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SEGS; ++k) {
+                const bf16x8 a = as_bf16x8(*(const uint4*)&As[16 * wave + (lane & 15)][32 * k + (lane >> 4) * 8]);
+#pragma unroll
+                for (int j = 0; j < BN / 16; ++j) {
+                    const bf16x8 b = as_bf16x8(*(const uint4*)&Bs[16 * j + (lane & 15)][32 * k + (lane >> 4) * 8]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+                }
             }
         }
     }
@@ -758,14 +775,24 @@ extern "C" int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_
     if (Cin % 32 || Cout % 32 || ((int64_t)H * W) % 64) return kEinval;
     const int64_t P = (int64_t)N * H * W;
     if (P / 64 > 0x7fffffff) return kEinval;
+    // 64 input channels per barrier pair where Cin allows it, else 32
+    const bool k64 = Cin % 64 == 0;
     if (Cout % 64 == 0) {
         dim3 g((unsigned)(P / 64), Cout / 64);
-        hipLaunchKernelGGL(conv3x3_fwd_k<64>, g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w, bias,
-                           Cout, relu, y);
+        if (k64)
+            hipLaunchKernelGGL((conv3x3_fwd_k<64, 64>), g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w,
+                               bias, Cout, relu, y);
+        else
+            hipLaunchKernelGGL((conv3x3_fwd_k<64, 32>), g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w,
+                               bias, Cout, relu, y);
     } else {
         dim3 g((unsigned)(P / 64), Cout / 32);
-        hipLaunchKernelGGL(conv3x3_fwd_k<32>, g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w, bias,
-                           Cout, relu, y);
+        if (k64)
+            hipLaunchKernelGGL((conv3x3_fwd_k<32, 64>), g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w,
+                               bias, Cout, relu, y);
+        else
+            hipLaunchKernelGGL((conv3x3_fwd_k<32, 32>), g, dim3(256), 0, (hipStream_t)stream, x, H, W, Cin, w,
+                               bias, Cout, relu, y);
     }
     return launch_status();
 }
