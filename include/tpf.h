@@ -175,8 +175,11 @@ int tpf_domain_size(tpf_ctx* ctx, int32_t id, int32_t* nx, int32_t* ny);
 /* Derived per-domain constants for inspection: k, gamma[3], gammaT, eta. */
 int tpf_derived(tpf_ctx* ctx, int32_t id, double* k, double* gamma3, double* gammaT, double* eta);
 
-/* Average duration (ms) of the fused step kernel over the steps issued since
- * the last call, measured with HIP events on the context's stream. */
+/* Average duration (ms) per launch of the fused step kernel over the steps
+ * issued since the last call while timing was enabled, measured with HIP
+ * events on the context's stream: one event pair around the launches of each
+ * tpf_step call (or each persistent launch), so the average includes the short
+ * gaps between back-to-back launches and no event sits between two of them. */
 int tpf_kernel_timing(tpf_ctx* ctx, int32_t enable, double* avg_ms, int64_t* launches);
 
 /* Roofline context, not part of the method: device-to-device copy of `bytes`
