@@ -300,6 +300,44 @@ struct StripShared {
     T psi[HAS_S ? 3 : 1][66];
 };
 
+// The LDS rings as one strip sees them: cell i of a phi row is column
+// x0 - 2 + i (i < 68), cell c of a mubar / psi row column x0 - 1 + c (c < 66).
+// A strip alone owns its rings and produces their halo cells itself.
+template <typename T, bool HAS_S>
+struct SoloRing {
+    StripShared<T, HAS_S>& s;
+    bool own_left = true, own_right = true;
+    __device__ T* phi0(int k) const { return s.phi0[k]; }
+    __device__ T* phi1(int k) const { return s.phi1[k]; }
+    __device__ T* mub(int k) const { return s.mub[k]; }
+    __device__ T* psi(int k) const { return s.psi[k]; }
+};
+
+// The NW strips of a lockstep group share one ring per field, 64 NW + 4 (phi)
+// or 64 NW + 2 (mubar, psi) cells wide: strip w's cells start at 64 w, so its
+// halo cells are its neighbours' edge cells, written by them in the same
+// phase of the same iteration.  Only the group's outer strips (and a strip
+// whose right neighbour lies past the domain) produce halo cells.
+template <typename T, bool HAS_S, int NW>
+struct GroupShared {
+    static constexpr int P = 64 * NW + 4, M = 64 * NW + 2;
+    T phi0[5][P];
+    T phi1[5][P];
+    T mub[3][M];
+    T psi[HAS_S ? 3 : 1][M];
+};
+
+template <typename T, bool HAS_S, int NW>
+struct GroupRing {
+    GroupShared<T, HAS_S, NW>& g;
+    int base;                     // 64 w
+    bool own_left, own_right;
+    __device__ T* phi0(int k) const { return g.phi0[k] + base; }
+    __device__ T* phi1(int k) const { return g.phi1[k] + base; }
+    __device__ T* mub(int k) const { return g.mub[k] + base; }
+    __device__ T* psi(int k) const { return g.psi[k] + base; }
+};
+
 // Load of a pulled population: non-temporal (NT) or plain.  Which is faster
 // depends on the tiling: within lockstep groups of 64-row strips NT loads
 // measured faster in FP32 (the DRAM streams run closer to copy speed, at the
@@ -355,8 +393,8 @@ __device__ __forceinline__ void wrap_cols(int x, int nx, uint32_t (&cb)[3]) {
 // each lane's source columns are fixed for the whole tile (cb: own column,
 // hb: the halo column of lanes 0..3) and every load uses scalar-base
 // addressing; otherwise the general pull with per-lane wall handling.
-template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT = 0>
-__device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, StripShared<T, HAS_S>& sh, int r, int x0,
+template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT, typename RG>
+__device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, const RG& sh, int r, int x0,
                                            int y0, int lane, int cur, bool dS, const uint32_t (&cb)[3],
                                            const uint32_t (&hb)[3], T (&fL)[9], T (&fU)[9],
                                            double* __restrict__ mom_out) {
@@ -378,11 +416,14 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     const int slot5 = r % 5;
     const int sy = map_index(yr, ny, py);
     const int cxh = lane < 2 ? lane : 64 + lane;   // halo cells 0, 1, 66, 67 (lanes 0..3)
+    // lanes 0, 1 produce the left halo cells, 2, 3 the right ones, where the
+    // strip owns them
+    const bool load_halo = lane < 2 ? sh.own_left : (lane < 4 && sh.own_right);
     T hF[9], p0v, h0v = T(0);
     if constexpr (PX) {
         pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, nx, ny, py, N, fL);
         p0v = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
-        if (lane < 4) {
+        if (load_halo) {
             pull9_cols<T, (NT & 2) != 0>(fin, hb, sy, nx, ny, py, N, hF);
             h0v = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
         }
@@ -390,7 +431,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
         const int sx = map_index(x, nx, px);
         pull9(fin, sx, sy, nx, ny, px, py, N, fL);
         p0v = phi0[sy * nx + sx];
-        if (lane < 4) {
+        if (load_halo) {
             const int hx = map_index(x0 - 2 + cxh, nx, px);
             pull9(fin, hx, sy, nx, ny, px, py, N, hF);
             h0v = phi0[sy * nx + hx];
@@ -419,14 +460,14 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
         T s = fL[0];
 #pragma unroll
         for (int q = 1; q < 9; ++q) s += fL[q];
-        sh.phi1[slot5][lane + 2] = s;
-        sh.phi0[slot5][lane + 2] = p0v;
-        if (lane < 4) {
+        sh.phi1(slot5)[lane + 2] = s;
+        sh.phi0(slot5)[lane + 2] = p0v;
+        if (load_halo) {
             T t = hF[0];
 #pragma unroll
             for (int q = 1; q < 9; ++q) t += hF[q];
-            sh.phi1[slot5][cxh] = t;
-            sh.phi0[slot5][cxh] = h0v;
+            sh.phi1(slot5)[cxh] = t;
+            sh.phi0(slot5)[cxh] = h0v;
         }
     }
     __syncthreads();
@@ -434,25 +475,27 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     // B. mubar1 (and psi) of row yr - 1 on 66 cells (x0 - 1 .. x0 + 64)
     const int slot3 = r % 3;
     if (r >= 2) {
-        const T* pm = sh.phi1[(r + 3) % 5];  // row yr - 2
-        const T* p0 = sh.phi1[(r + 4) % 5];  // row yr - 1
-        const T* pp = sh.phi1[slot5];        // row yr
-        const T* qm = sh.phi0[(r + 3) % 5];
-        const T* q0 = sh.phi0[(r + 4) % 5];
-        const T* qp = sh.phi0[slot5];
+        const T* pm = sh.phi1((r + 3) % 5);  // row yr - 2
+        const T* p0 = sh.phi1((r + 4) % 5);  // row yr - 1
+        const T* pp = sh.phi1(slot5);        // row yr
+        const T* qm = sh.phi0((r + 3) % 5);
+        const T* q0 = sh.phi0((r + 4) % 5);
+        const T* qp = sh.phi0(slot5);
         for (int c = lane; c < 66; c += 64) {
+            // the halo cells 0 and 65 only where the strip owns them
+            if ((c == 0 && !sh.own_left) || (c == 65 && !sh.own_right)) continue;
             const int i = c + 1;
             const T l1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
                           (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
             const T l0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
                           (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
             T mu0, mu1, mu2;
-            sh.mub[slot3][c] = mubar1<T>(K, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
+            sh.mub(slot3)[c] = mubar1<T>(K, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
             if constexpr (HAS_S) {
                 if (dS) {
                     const int sx = map_index(x0 - 1 + c, nx, px);
                     const int sy = map_index(yr - 1, ny, py);
-                    sh.psi[slot3][c] = gpc<T>(d.psi[cur])[sy * nx + sx];
+                    sh.psi(slot3)[c] = gpc<T>(d.psi[cur])[sy * nx + sx];
                 }
             }
         }
@@ -463,15 +506,15 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     if (do_update) {
         const int i = lane + 2;   // phi cell of the node
         const int j = lane + 1;   // mubar cell of the node
-        const T* pm = sh.phi1[(r + 2) % 5];  // row yu - 1
-        const T* p0 = sh.phi1[(r + 3) % 5];  // row yu
-        const T* pp = sh.phi1[(r + 4) % 5];  // row yu + 1
-        const T* qm = sh.phi0[(r + 2) % 5];
-        const T* q0 = sh.phi0[(r + 3) % 5];
-        const T* qp = sh.phi0[(r + 4) % 5];
-        const T* mm = sh.mub[(r + 1) % 3];   // row yu - 1
-        const T* m0 = sh.mub[(r + 2) % 3];   // row yu
-        const T* mp = sh.mub[slot3];         // row yu + 1
+        const T* pm = sh.phi1((r + 2) % 5);  // row yu - 1
+        const T* p0 = sh.phi1((r + 3) % 5);  // row yu
+        const T* pp = sh.phi1((r + 4) % 5);  // row yu + 1
+        const T* qm = sh.phi0((r + 2) % 5);
+        const T* q0 = sh.phi0((r + 3) % 5);
+        const T* qp = sh.phi0((r + 4) % 5);
+        const T* mm = sh.mub((r + 1) % 3);   // row yu - 1
+        const T* m0 = sh.mub((r + 2) % 3);   // row yu
+        const T* mp = sh.mub(slot3);         // row yu + 1
         const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) * T(1.0 / 12.0);
         const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) * T(1.0 / 12.0);
         const T lap1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
@@ -485,9 +528,9 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
         T dpx = T(0), dpy = T(0);
         if constexpr (HAS_S) {
             if (dS) {
-                const T* sm = sh.psi[(r + 1) % 3];
-                const T* s0 = sh.psi[(r + 2) % 3];
-                const T* sp = sh.psi[slot3];
+                const T* sm = sh.psi((r + 1) % 3);
+                const T* s0 = sh.psi((r + 2) % 3);
+                const T* sp = sh.psi(slot3);
                 dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) * T(1.0 / 12.0);
                 dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
@@ -498,9 +541,9 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
 }
 
 // One (domain, strip, chunk) tile of the strip kernel at the given step offset.
-template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT = 0>
-__device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
-                                           int step_offset, double* __restrict__ mom_out) {
+template <typename T, int CH, bool HAS_S, int MODE, bool PX, int NT, typename RG>
+__device__ __forceinline__ void strip_rows(const DomDev& d, const RG& sh, int x0, int y0, int step_offset,
+                                           double* __restrict__ mom_out) {
     const KConst<T> K = kconst<T>(d);
     const int cur = (d.parity + step_offset) & 1;
     const bool dS = HAS_S && d.has_s;
@@ -516,19 +559,26 @@ __device__ __forceinline__ void strip_rows(const DomDev& d, StripShared<T, HAS_S
     // (the row loaded two iterations earlier)
     constexpr int R = CH + 4;
     for (int r = 0; r < R; r += 3) {
-        strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r, x0, y0, lane, cur, dS, cb, hb, F0, F1, mom_out);
+        strip_iter<T, CH, HAS_S, MODE, PX, NT, RG>(d, K, sh, r, x0, y0, lane, cur, dS, cb, hb, F0, F1, mom_out);
         if (r + 1 < R)
-            strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r + 1, x0, y0, lane, cur, dS, cb, hb, F1, F2, mom_out);
+            strip_iter<T, CH, HAS_S, MODE, PX, NT, RG>(d, K, sh, r + 1, x0, y0, lane, cur, dS, cb, hb, F1, F2, mom_out);
         if (r + 2 < R)
-            strip_iter<T, CH, HAS_S, MODE, PX, NT>(d, K, sh, r + 2, x0, y0, lane, cur, dS, cb, hb, F2, F0, mom_out);
+            strip_iter<T, CH, HAS_S, MODE, PX, NT, RG>(d, K, sh, r + 2, x0, y0, lane, cur, dS, cb, hb, F2, F0, mom_out);
     }
+}
+
+template <typename T, int CH, bool HAS_S, int MODE, int NT, typename RG>
+__device__ __forceinline__ void strip_tile_r(const DomDev& d, const RG& ring, int x0, int y0, int step_offset,
+                                             double* __restrict__ mom_out) {
+    if (d.px) strip_rows<T, CH, HAS_S, MODE, true, NT, RG>(d, ring, x0, y0, step_offset, mom_out);
+    else strip_rows<T, CH, HAS_S, MODE, false, NT, RG>(d, ring, x0, y0, step_offset, mom_out);
 }
 
 template <typename T, int CH, bool HAS_S, int MODE, int NT = 0>
 __device__ __forceinline__ void strip_tile(const DomDev& d, StripShared<T, HAS_S>& sh, int x0, int y0,
                                            int step_offset, double* __restrict__ mom_out) {
-    if (d.px) strip_rows<T, CH, HAS_S, MODE, true, NT>(d, sh, x0, y0, step_offset, mom_out);
-    else strip_rows<T, CH, HAS_S, MODE, false, NT>(d, sh, x0, y0, step_offset, mom_out);
+    const SoloRing<T, HAS_S> ring{sh};
+    strip_tile_r<T, CH, HAS_S, MODE, NT>(d, ring, x0, y0, step_offset, mom_out);
 }
 
 template <typename T, int CH, bool HAS_S, int MODE>
@@ -619,10 +669,9 @@ strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, in
 // workgroup barriers, so the NW strips advance row by row in lockstep and the
 // columns that neighbouring strips share (their stencil and pull halos) are
 // read while the other strip's wavefront holds the same cache lines.
-template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT>
-__device__ __forceinline__ void strip_group_body(StripShared<T, HAS_S>* sh, const DomDev* __restrict__ doms,
-                                                 const int4* __restrict__ tiles, int ntiles, int step_offset,
-                                                 double* __restrict__ mom_out) {
+template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT, bool SHARE>
+__device__ __forceinline__ void strip_group_body(const DomDev* __restrict__ doms, const int4* __restrict__ tiles,
+                                                 int ntiles, int step_offset, double* __restrict__ mom_out) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= ntiles) return;
     const int4 tile = tiles[t];
@@ -640,31 +689,40 @@ __device__ __forceinline__ void strip_group_body(StripShared<T, HAS_S>* sh, cons
         }
         return;
     }
-    strip_tile<T, CH, HAS_S, MODE, NT>(d, sh[w], x0, tile.z, step_offset, mom_out);
+    if constexpr (SHARE) {
+        // one ring per field for the whole group: the outer strips of the
+        // group, and a strip whose right neighbour lies past the domain's
+        // last column, produce the halo cells on that side
+        static_assert(sizeof(GroupShared<T, HAS_S, NW>) <= 65536, "LDS of a workgroup is limited to 64 KB");
+        __shared__ GroupShared<T, HAS_S, NW> g;
+        const GroupRing<T, HAS_S, NW> ring{g, 64 * w, w == 0, w == NW - 1 || x0 + 64 >= d.nx};
+        strip_tile_r<T, CH, HAS_S, MODE, NT>(d, ring, x0, tile.z, step_offset, mom_out);
+    } else {
+        // a ring per strip, each with its own halo cells
+        static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
+        __shared__ StripShared<T, HAS_S> sh[NW];
+        strip_tile<T, CH, HAS_S, MODE, NT>(d, sh[w], x0, tile.z, step_offset, mom_out);
+    }
 }
 
-// Compiled for four wavefronts per SIMD (at most 128 VGPRs): the FP32 step
-// fits without spills.
-template <typename T, int CH, bool HAS_S, int MODE, int NW>
+// Compiled for four wavefronts per SIMD (at most 128 VGPRs).  SHARE: the
+// strips share one LDS ring per field (halo cells from the neighbours).
+template <typename T, int CH, bool HAS_S, int MODE, int NW, bool SHARE>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
 strip_group_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
                    int step_offset, double* __restrict__ mom_out) {
-    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
-    __shared__ StripShared<T, HAS_S> sh[NW];
-    strip_group_body<T, CH, HAS_S, MODE, NW, 0>(sh, doms, tiles, ntiles, step_offset, mom_out);
+    strip_group_body<T, CH, HAS_S, MODE, NW, 0, SHARE>(doms, tiles, ntiles, step_offset, mom_out);
 }
 
 // The same groups with the register budget left to the compiler (the FP64
 // step takes about 230 VGPRs, two wavefronts per SIMD), so the FP64 build
 // gets the shared halos without spilling.  NT selects non-temporal loads of
 // the pulled populations: bit 0 the NS lattice g, bit 1 the CH lattice f.
-template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT>
+template <typename T, int CH, bool HAS_S, int MODE, int NW, int NT, bool SHARE>
 __global__ void __launch_bounds__(64 * NW)
 strip_group_kernel_wide(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
                         int step_offset, double* __restrict__ mom_out) {
-    static_assert(sizeof(StripShared<T, HAS_S>) * NW <= 65536, "LDS of a workgroup is limited to 64 KB");
-    __shared__ StripShared<T, HAS_S> sh[NW];
-    strip_group_body<T, CH, HAS_S, MODE, NW, NT>(sh, doms, tiles, ntiles, step_offset, mom_out);
+    strip_group_body<T, CH, HAS_S, MODE, NW, NT, SHARE>(doms, tiles, ntiles, step_offset, mom_out);
 }
 
 // Same kernel compiled for five wavefronts per SIMD (fewer registers, a few

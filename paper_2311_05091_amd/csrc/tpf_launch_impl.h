@@ -22,16 +22,16 @@ hipError_t launch_strip_t(const TileLaunch& a) {
     return hipGetLastError();
 }
 
-template <typename T, int CH, bool S, int MODE, int NW>
+template <typename T, int CH, bool S, int MODE, int NW, bool SHARE>
 hipError_t launch_strip_group_t(const TileLaunch& a) {
-    hipLaunchKernelGGL((strip_group_kernel<T, CH, S, MODE, NW>), dim3(a.ntiles), dim3(64 * NW), 0, a.stream,
+    hipLaunchKernelGGL((strip_group_kernel<T, CH, S, MODE, NW, SHARE>), dim3(a.ntiles), dim3(64 * NW), 0, a.stream,
                        a.doms, a.tiles, a.ntiles, a.offset, a.mom);
     return hipGetLastError();
 }
 
-template <typename T, int CH, bool S, int MODE, int NW, int NT>
+template <typename T, int CH, bool S, int MODE, int NW, int NT, bool SHARE>
 hipError_t launch_strip_group_wide_t(const TileLaunch& a) {
-    hipLaunchKernelGGL((strip_group_kernel_wide<T, CH, S, MODE, NW, NT>), dim3(a.ntiles), dim3(64 * NW), 0, a.stream,
+    hipLaunchKernelGGL((strip_group_kernel_wide<T, CH, S, MODE, NW, NT, SHARE>), dim3(a.ntiles), dim3(64 * NW), 0, a.stream,
                        a.doms, a.tiles, a.ntiles, a.offset, a.mom);
     return hipGetLastError();
 }
@@ -53,13 +53,13 @@ hipError_t launch_strip2_t(const TileLaunch& a) {
 template <typename T, bool S, int MODE>
 hipError_t launch_shape(int code, const TileLaunch& a) {
     switch (code) {
-        case 17: return launch_strip_group_t<T, 32, S, MODE, 4>(a);
-        case 18: return launch_strip_group_t<T, 32, S, MODE, 2>(a);
-        case 20: return launch_strip_group_t<T, 16, S, MODE, 4>(a);
-        case 21: return launch_strip_group_wide_t<T, 32, S, MODE, 4, 0>(a);
-        case 22: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 0>(a);
-        case 23: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 3>(a);
-        case 24: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 1>(a);
+        case 17: return launch_strip_group_t<T, 32, S, MODE, 4, true>(a);
+        case 18: return launch_strip_group_t<T, 32, S, MODE, 2, true>(a);
+        case 20: return launch_strip_group_t<T, 16, S, MODE, 4, true>(a);
+        case 21: return launch_strip_group_wide_t<T, 32, S, MODE, 4, 0, true>(a);
+        case 22: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 0, true>(a);
+        case 23: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 3, false>(a);
+        case 24: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 1, true>(a);
         case 15: return launch_strip_o5_t<T, 32, S, MODE>(a);
         case 16: return launch_strip_o5_t<T, 16, S, MODE>(a);
         case 12: return launch_strip2_t<T, 16, S, MODE>(a);
