@@ -25,20 +25,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
 
-# HBM traffic per launch of the step kernel on the porous 4096 x 2048
-# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
-# scaled by the factors a plain copy kernel of known size gives (1.99974 or
-# 1.99975, and 1.0), for groups of four 64 x 64 strips: FP32 tile code 23
-# (non-temporal population loads) 399588.1 KiB x 1.99974 + 688128.0 KiB;
-# FP64 tile code 22 750280.8 KiB x 1.99975 + 1376257.2 KiB; FP64 tile code 24
-# (non-temporal NS loads) 755688.1 KiB x 1.99974 + 1376257.9 KiB.  Reported
-# only for those tile codes, workload and precisions; removed whenever the
-# kernel source changes after the counters were taken.
-PMC_TRAFFIC_BYTES = {(23, 32, "porous_displacement_4096x2048"): 1.5229e9,
-                     (22, 64, "porous_displacement_4096x2048"): 2.9457e9,
-                     (24, 64, "porous_displacement_4096x2048"): 2.9567e9,
-                     # batched sweep, FP32 tile code 20: 3290843.2 x 1.99974 + 5257530.9 KiB
-                     (20, 32, "batched_sweep_512_domains_60280697_nodes"): 1.2122e10}
+# HBM traffic per launch of the step kernel, from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch) scaled by the factors a plain copy kernel
+# of known size gives (1.99974 or 1.99975, and 1.0), for the tile codes the
+# autotuner takes: porous 4096 x 2048 FP32 code 23 397479.2 KiB x 1.99975 +
+# 688128.1 KiB; FP64 code 24 764488.8 KiB x 1.99974 + 1376258.6 KiB; batched
+# sweep FP32 code 21 3111792.0 KiB x 1.99975 + 5216502.8 KiB.  Reported only
+# for those tile codes, workloads and precisions; removed whenever the kernel
+# source changes after the counters were taken.
+PMC_TRAFFIC_BYTES = {(23, 32, "porous_displacement_4096x2048"): 1.5186e9,
+                     (24, 64, "porous_displacement_4096x2048"): 2.9748e9,
+                     (21, 32, "batched_sweep_512_domains_60280697_nodes"): 1.1714e10}
 
 
 def workload(name: str, nx: int = 4096, ny: int = 2048):
