@@ -7,9 +7,15 @@ deg, density ratio 1, viscosity ratio 5, body force 1e-6 along x.  A step is
 one coupled update of both lattices at every node (one launch of the fused
 kernel).  Inputs are resident in HBM before the timed region.
 
+Between the warmup steps and the timed region a settle phase keeps the device
+stepping for --settle-s seconds (reported as settle_s / settle_steps): after
+an idle gap the first few dozen launches run slower than the steady state.
+
 Prints one JSON line: coupled MLUPS (whole-job), the roofline of the fused
 kernel (algorithmic bytes per launch / HIP-event kernel time against the
-8 TB/s HBM peak) and the CPU oracle timed on a bounded sample.
+8 TB/s HBM peak) and the CPU oracle timed on a bounded sample.  roofline.traffic
+is null: the HBM traffic counters need a profiler run of their own; their
+figures for each kernel are kept with its profile summary.
 """
 from __future__ import annotations
 
@@ -24,19 +30,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "coupled MLUPS + % HBM roofline; time-to-equilibrium learned vs plain"
-
-# HBM traffic per launch of the step kernel, from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE (KiB per dispatch) scaled by the factors a plain copy kernel
-# of known size gives (1.99974 or 1.99975, and 1.0), for the tile codes the
-# autotuner takes: porous 4096 x 2048 FP32 code 23 397479.2 KiB x 1.99975 +
-# 688128.1 KiB; FP64 code 24 764488.8 KiB x 1.99974 + 1376258.6 KiB; batched
-# sweep FP32 code 21 3111792.0 KiB x 1.99975 + 5216502.8 KiB.  Reported only
-# for those tile codes, workloads and precisions; removed whenever the kernel
-# source changes after the counters were taken.
-PMC_TRAFFIC_BYTES = {(23, 32, "porous_displacement_4096x2048"): 1.5186e9,
-                     (24, 64, "porous_displacement_4096x2048"): 2.9748e9,
-                     (21, 32, "batched_sweep_512_domains_60280697_nodes"): 1.1714e10}
-
 
 def workload(name: str, nx: int = 4096, ny: int = 2048):
     from paper_2311_05091_amd import geometry as G
@@ -85,6 +78,10 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
     ap.add_argument("--launch-mode", type=int, default=0,
                     help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
+    ap.add_argument("--settle-s", type=float, default=0.3,
+                    help="seconds of untimed steps run right before the timed region, after the "
+                         "warmup steps: after an idle gap of even 50 ms the device runs the first "
+                         "~60 launches 5-18%% slower than in steady state")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy-ceiling", dest="copy_ceiling", action="store_false",
@@ -133,6 +130,16 @@ def main():
     print("[bench] tile %d (%dx%d), launch mode %d" % (code, tx, ty, args.launch_mode), flush=True)
     ctx.step(args.warmup)
     torch.cuda.synchronize()
+    # settle: keep the device busy until its clocks hold their steady state, so
+    # that the timed launches do not start on a ramp (each call returns after
+    # the stream has drained; the gaps between calls are microseconds)
+    settle_steps = 0
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        ctx.step(25)
+        settle_steps += 25
+    torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
 
     ctx.kernel_timing(True)
     torch.cuda.synchronize()
@@ -150,14 +157,15 @@ def main():
     achieved = bpn * nodes / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if args.launch_mode else PMC_TRAFFIC_BYTES.get((code, args.precision, wname)),
+            "traffic": None,
             "bytes_per_node": bpn, "kernel_ms": round(kern_ms, 5)}
     if copy_gbs:
         roof["copy_GBs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "steps": args.steps, "warmup": args.warmup, "settle_s": round(settle_s, 3),
+        "settle_steps": settle_steps, "ms_per_step": round(dt / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
         "config": {"workload": wname, "nodes": nodes, "lattice": "D2Q9 x 2 (CH + NS)",
