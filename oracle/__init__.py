@@ -46,6 +46,7 @@ class Params(C.Structure):
         ("M_cst", C.c_double), ("M_deg", C.c_double), ("tau_phi", C.c_double),
         ("s_phi", C.c_double * 4), ("s_g", C.c_double * 4),
         ("Fb", C.c_double * 2), ("u_wall", C.c_double * 2),
+        ("omega_wall", C.c_double), ("wall_center", C.c_double * 2),
         ("rho_gauge", C.c_double),
     ]
 
@@ -64,9 +65,10 @@ _D = C.POINTER(C.c_double)
 def _lib_handle():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = os.environ.get("TPF_ORACLE_LIB", _LIB_PATH)
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             build(force=True)
-        lib = C.CDLL(_LIB_PATH)
+        lib = C.CDLL(path)
         lib.orc_create.restype = C.c_void_p
         lib.orc_create.argtypes = [C.POINTER(Params), _D, _D]
         lib.orc_free.argtypes = [C.c_void_p]
@@ -127,7 +129,7 @@ def make_params(nx, ny, *, periodic_x=1, periodic_y=0, d0=0.5, D=4.0, sigma12=0.
                 theta_deg=60.0, kappa=0.0, rho=(1.0, 1.0, 1.0), mu=(0.15, 0.15, 0.15),
                 M_cst=0.0, M_deg=0.1, tau_phi=0.8, s_phi=(1.0, 1.0, 1.0, 1.0),
                 s_g=(1.0, 1.0, 1.0, 1.0), Fb=(0.0, 0.0), u_wall=(0.0, 0.0),
-                rho_gauge=0.0) -> Params:
+                omega_wall=0.0, wall_center=(0.0, 0.0), rho_gauge=0.0) -> Params:
     p = Params()
     p.nx, p.ny, p.periodic_x, p.periodic_y = nx, ny, periodic_x, periodic_y
     p.d0, p.D, p.sigma12 = d0, D, sigma12
@@ -139,6 +141,8 @@ def make_params(nx, ny, *, periodic_x=1, periodic_y=0, d0=0.5, D=4.0, sigma12=0.
     p.s_g[:] = list(s_g)
     p.Fb[:] = list(Fb)
     p.u_wall[:] = list(u_wall)
+    p.omega_wall = omega_wall
+    p.wall_center[:] = list(wall_center)
     p.rho_gauge = rho_gauge
     return p
 

@@ -40,6 +40,10 @@
  *       (s -> 0) at phi0 = 1.
  *   R11 in the 2D pressure constant H the term (2 - 4 d0)/s2a is zero when its
  *       coefficient is zero (d0 = 1/2), also at saturated solid nodes (s2a = 0).
+ *   R19 the solid-point velocity u_w of f = (u_w - u*)/dt (Sec. 3) is that of a
+ *       rigid body: u_w(x) = u_wall + omega_wall e_z x (x - wall_center), with
+ *       the solid field phi0 held fixed (a solid whose shape is invariant under
+ *       its own motion: a sliding plate, a spinning cylinder).
  */
 #include <math.h>
 #include <stdint.h>
@@ -64,7 +68,9 @@ typedef struct {
     double s_phi[4];    /* s0, s2, s3, s4 of the CH lattice               */
     double s_g[4];      /* s0, s1, s3, s4 of the NS lattice               */
     double Fb[2];       /* body force                                     */
-    double u_wall[2];   /* solid velocity u_w                             */
+    double u_wall[2];   /* translation of the solid                       */
+    double omega_wall;  /* angular velocity of the solid about wall_center */
+    double wall_center[2];
     double rho_gauge;   /* constant in lambda_0                           */
 } orc_params;
 
@@ -521,7 +527,10 @@ static void macro_and_collide(orc_sim* s, int collide)
             double jx = 0.0, jy = 0.0;
             for (int i = 0; i < 9; ++i) { jx += CX[i] * gl[i]; jy += CY[i] * gl[i]; }
             double usx = (jx + 0.5 * Fx) / rho, usy = (jy + 0.5 * Fy) / rho;
-            double fsx = P->u_wall[0] - usx, fsy = P->u_wall[1] - usy;
+            /* rigid-body velocity of the solid point (reading R19) */
+            double uwx = P->u_wall[0] - P->omega_wall * (y - P->wall_center[1]);
+            double uwy = P->u_wall[1] + P->omega_wall * (x - P->wall_center[0]);
+            double fsx = uwx - usx, fsy = uwy - usy;
             double ux = usx + 0.5 * phi0 * fsx, uy = usy + 0.5 * phi0 * fsy;
             double Gx = Fx + phi0 * rho * fsx, Gy = Fy + phi0 * rho * fsy;
 

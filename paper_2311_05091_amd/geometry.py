@@ -43,6 +43,8 @@ class DomainSpec:
     s_g: tuple = (1.0, 1.0, 1.0, 1.0)
     Fb: tuple = (0.0, 0.0)
     u_wall: tuple = (0.0, 0.0)
+    omega_wall: float = 0.0
+    wall_center: tuple = (0.0, 0.0)
     rho_gauge: float = 0.0
     name: str = ""
 

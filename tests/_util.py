@@ -6,7 +6,8 @@ def oracle_params(orc, sp, **kw):
     d = dict(periodic_x=sp.periodic_x, periodic_y=sp.periodic_y, d0=sp.d0, D=sp.D,
              sigma12=sp.sigma12, theta_deg=sp.theta_deg, kappa=sp.kappa, rho=sp.rho, mu=sp.mu,
              M_cst=sp.M_cst, M_deg=sp.M_deg, tau_phi=sp.tau_phi, s_phi=sp.s_phi, s_g=sp.s_g,
-             Fb=sp.Fb, u_wall=sp.u_wall, rho_gauge=sp.rho_gauge)
+             Fb=sp.Fb, u_wall=sp.u_wall, omega_wall=sp.omega_wall,
+             wall_center=sp.wall_center, rho_gauge=sp.rho_gauge)
     d.update(kw)
     return orc.make_params(sp.nx, sp.ny, **d)
 

@@ -1,0 +1,74 @@
+"""The oracle's pins catch plausible mistakes in the terms they pin.
+
+Each case plants one mistake in a copy of oracle/tpf_oracle.c (a text
+substitution: a dropped term, a flipped sign, a wrong factor), compiles it with
+gcc into a temporary library and runs the pin that must catch it, in a
+subprocess that loads the mutant (TPF_ORACLE_LIB).  The pin must fail.  A
+control case runs the same harness on the unchanged source, whose pins must
+pass.  Everything here runs on the CPU; the GPU library is not involved.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "tpf_oracle.c")
+NORMAL = "tests/test_oracle_consistency.py::test_translating_interface_density_ratio_10"
+TANGENT = "tests/test_oracle_consistency.py::test_tangential_flow_along_relaxing_interface"
+CHANNEL = "tests/test_oracle_solid.py::test_diffuse_channel_momentum_balance"
+SLIDE = "tests/test_oracle_solid.py::test_sliding_solid_adds_its_velocity"
+SPIN = "tests/test_oracle_solid.py::test_spinning_cavity_rigid_rotation"
+
+# name, original text (must occur exactly once), replacement, pin that must fail
+MUTANTS = [
+    ("pressure_no_u_grad_rho", "(sum + (0.5 + H) * u_grad_rho", "(sum + 0.0 * u_grad_rho", NORMAL),
+    ("pressure_H_sign", "(sum + (0.5 + H) * u_grad_rho", "(sum + (0.5 - H) * u_grad_rho", NORMAL),
+    ("pressure_omega0_sign", "- w[0] * B / (1.0 - cs2)", "+ w[0] * B / (1.0 - cs2)", NORMAL),
+    ("M2F_no_density_gradient", "+ 2.0 * cs2 * ux * drx + (1.0 - 3.0 * cs2) * Q;", "+ (1.0 - 3.0 * cs2) * Q;",
+     NORMAL),
+    ("M2F_no_isotropic_Q", "+ 2.0 * cs2 * ux * drx + (1.0 - 3.0 * cs2) * Q;", "+ 2.0 * cs2 * ux * drx;", NORMAL),
+    ("Fpop_no_Q", "F[i] = w[i] * (Q + (CX[i]", "F[i] = w[i] * (0.0 * Q + (CX[i]", NORMAL),
+    ("Fc_sign", "double Fcx = -0.5 * dpsiy, Fcy = 0.5 * dpsix;", "double Fcx = 0.5 * dpsiy, Fcy = -0.5 * dpsix;",
+     TANGENT),
+    ("Fc_dropped", "double Fcx = -0.5 * dpsiy, Fcy = 0.5 * dpsix;", "double Fcx = 0.0 * dpsiy, Fcy = 0.0 * dpsix;",
+     TANGENT),
+    ("geq_no_S_in_shear_flux", "double Pixy = rho * ux * uy - 0.5 * (Sx * uy + ux * Sy);",
+     "double Pixy = rho * ux * uy;", TANGENT),
+    ("S_sign", "double Sx = (rho1 - rho2) * Mob / d->gamma[1] * gmx;",
+     "double Sx = -(rho1 - rho2) * Mob / d->gamma[1] * gmx;", TANGENT),
+    ("penalty_full_correction", "double ux = usx + 0.5 * phi0 * fsx", "double ux = usx + 1.0 * phi0 * fsx", CHANNEL),
+    ("penalty_force_doubled", "double Gx = Fx + phi0 * rho * fsx", "double Gx = Fx + 2.0 * phi0 * rho * fsx",
+     CHANNEL),
+    ("viscosity_without_solid_factor", "return (1.0 - phi0) / (mu_v / (rho * cfac) + 0.5 * (1.0 - phi0));",
+     "return 1.0 / (mu_v / (rho * cfac) + 0.5);", CHANNEL),
+    ("wall_velocity_sign", "double uwx = P->u_wall[0] - P->omega_wall", "double uwx = -P->u_wall[0] - P->omega_wall",
+     SLIDE),
+    ("wall_velocity_half", "double fsx = uwx - usx", "double fsx = 0.5 * uwx - usx", SLIDE),
+    ("rotation_sign", "double uwy = P->u_wall[1] + P->omega_wall", "double uwy = P->u_wall[1] - P->omega_wall", SPIN),
+]
+
+
+def _run_pin(tmp_path, name, src_text, pin):
+    c = tmp_path / (name + ".c")
+    so = tmp_path / (name + ".so")
+    c.write_text(src_text)
+    subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c),
+                           "-lm"])
+    env = dict(os.environ, TPF_ORACLE_LIB=str(so))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_unchanged_oracle_passes_through_the_harness(tmp_path):
+    r = _run_pin(tmp_path, "control", open(SRC).read(), NORMAL)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name,orig,repl,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_fails_its_pin(tmp_path, name, orig, repl, pin):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, "mutation site changed: " + orig
+    r = _run_pin(tmp_path, name, src.replace(orig, repl), pin)
+    assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
