@@ -125,3 +125,56 @@ def test_mass_project_recovers_a_known_shift():
         assert np.all(f >= 0) and np.all(f <= 1.0 - phi0 + 1e-15)
     with pytest.raises(ValueError):
         O.mass_project(pred, phi0, 2.0 * np.sum(1.0 - phi0))
+
+
+def test_avgpool_of_constant_and_ramp_fields():
+    """2x2 average pooling keeps a constant field (a sum-pool would scale it
+    by 4) and maps a ramp x to the mean of each pair, x + 1/2."""
+    c = np.full((1, 6, 8, 3), 2.5)
+    assert np.array_equal(O.avgpool2(c), np.full((1, 3, 4, 3), 2.5))
+    ramp = np.tile(np.arange(8.0)[None, None, :, None], (2, 4, 1, 1))
+    pooled = O.avgpool2(ramp)
+    assert np.allclose(pooled[..., 0], np.arange(0, 8, 2)[None, None, :] + 0.5)
+
+
+@pytest.mark.parametrize("t_end", [2, 5])
+def test_adam_constant_gradient_closed_form(t_end):
+    """Under a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step t, so each step moves by lr g/(|g| + eps): after t
+    steps p = p0 - t lr g/(|g| + eps).  A bias correction with the wrong power
+    of beta breaks this from t = 2 on."""
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    p0 = np.array([1.0, -1.0, 0.5, 2.0])
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    for t in range(1, t_end + 1):
+        p, m, v = O.adam(p, m, v, g, lr, b1, b2, eps, t)
+    expect = p0 - t_end * lr * g / (np.abs(g) + eps)
+    assert np.allclose(p, expect, rtol=0, atol=1e-12)
+
+
+def test_unet_wiring_with_hand_set_weights():
+    """A two-level network of one channel per layer whose convolutions are the
+    centre tap (identity) except the decoder's first convolution after the
+    concatenation, which weighs the upsampled path by a and the skip by b:
+    for a non-negative input x (ReLU passes) the last activation is
+    a upsample(avgpool(x)) + b x, and the head with weight 1 and bias -0.3
+    gives sigmoid of that minus 0.3.  Pins the order of pooling, upsampling,
+    concatenation (upsampled path first) and which skip joins which level."""
+    rng2 = np.random.default_rng(3)
+    x = rng2.uniform(0.0, 1.0, size=(2, 8, 8, 1))
+
+    def ident(cin=1):
+        w = np.zeros((1, 3, 3, cin))
+        w[0, 1, 1, 0] = 1.0
+        return w, np.zeros(1)
+    a, b = 0.7, 0.2
+    wcat = np.zeros((1, 3, 3, 2))
+    wcat[0, 1, 1, 0], wcat[0, 1, 1, 1] = a, b
+    params = {"e0a": ident(), "e0b": ident(), "e1a": ident(), "e1b": ident(), "d0u": ident(),
+              "d0a": (wcat, np.zeros(1)), "d0b": ident(), "head": (np.ones(1), -0.3)}
+    acts = O.unet_forward(params, x, widths=(1, 1))
+    expect = a * O.upsample2(O.avgpool2(x)) + b * x
+    assert np.allclose(acts["last"], expect, atol=1e-14)
+    pred = O.head(acts["last"], *params["head"])
+    assert np.allclose(pred, 1.0 / (1.0 + np.exp(-(expect[..., 0] - 0.3))), atol=1e-14)
