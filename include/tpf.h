@@ -61,7 +61,14 @@ typedef struct {
     double s_g[4];                /* s0, s1, s3, s4 of the NS lattice; 1 (s2a, s2b follow
                                      per node from the viscosity relation of Sec. 3)   */
     double Fb[2];                 /* body force F_b (Sec. 2.3)                          */
-    double u_wall[2];             /* solid velocity u_w in f = (u_w - u*)/dt (Sec. 3)   */
+    double u_wall[2];             /* velocity u_w of the solid points in f = (u_w - u*)/dt
+                                     (Sec. 3): a rigid motion, u_w(x, y) = u_wall +
+                                     omega_wall e_z x ((x, y) - wall_center), node (i, j)
+                                     at (x, y) = (i, j); phi0 stays fixed, so the motion
+                                     must leave the solid's shape invariant (a sliding
+                                     plate, a spinning disk or ring); 0                   */
+    double omega_wall;            /* angular velocity of the solid; 0                   */
+    double wall_center[2];        /* centre of that rotation; 0                         */
     double rho_gauge;             /* constant in lambda_0 (Sec. 3); 0 = offset storage   */
 } tpf_domain_params;
 
@@ -134,7 +141,13 @@ int tpf_set_active(tpf_ctx* ctx, int32_t id, int32_t active);
  * g[9][ny][nx]) as float64, for checkpoints and tests; either may be NULL. */
 int tpf_get_populations(tpf_ctx* ctx, int32_t id, double* f, double* g);
 
-/* Checkpoint / restart of the whole context (same build, same domains). */
+/* Checkpoint / restart of the whole context (same build, same domains).
+ * tpf_load checks the whole file before it changes any state: TPF_EINVAL when
+ * the file holds another precision, another number of domains or any domain
+ * whose parameters differ from the context's in any field; TPF_EIO when the
+ * file cannot be opened or is shorter than its header promises.  Only a file
+ * that changes while it is being loaded can leave the context part-loaded
+ * (TPF_EIO). */
 int tpf_save(tpf_ctx* ctx, const char* path);
 int tpf_load(tpf_ctx* ctx, const char* path);
 

@@ -179,6 +179,9 @@ static int validate(const tpf_domain_params& p) {
         if (!(p.s_phi[i] > 0.0 && p.s_phi[i] < 2.0) || !(p.s_g[i] > 0.0 && p.s_g[i] < 2.0))
             return TPF_EINVAL;
     if (!(p.kappa > -1.0)) return TPF_EINVAL;
+    if (!std::isfinite(p.omega_wall) || !std::isfinite(p.wall_center[0]) || !std::isfinite(p.wall_center[1]) ||
+        !std::isfinite(p.u_wall[0]) || !std::isfinite(p.u_wall[1]))
+        return TPF_EINVAL;
     double k, g[3], gT;
     derive_gamma(p, k, g, gT);
     if (!(g[0] > 0 && g[1] > 0 && g[2] > 0)) return TPF_EINVAL;
@@ -228,6 +231,9 @@ static void fill_kconst(const tpf_domain_params& p, const HostDomain& h, KConst<
     K.Fby = (T)p.Fb[1];
     K.uwx = (T)p.u_wall[0];
     K.uwy = (T)p.u_wall[1];
+    K.om = (T)p.omega_wall;
+    K.xc = (T)p.wall_center[0];
+    K.yc = (T)p.wall_center[1];
     K.gauge = (T)p.rho_gauge;
     // p = c_s^2/(1 - w0) [ sum_{i != 0} g_i + (1/2 + H) u.grad(rho)
     //      - w0 (rho u - S).u/(c^2 - c_s^2) + (K/c^2)(dt/2) d_t((rho u - S).u) ]
@@ -813,7 +819,7 @@ extern "C" int tpf_get_populations(tpf_ctx* c, int32_t id, double* f, double* g)
 
 // Checkpoint: a header, then per domain its host bookkeeping and its whole
 // arena slice (populations of both buffers, phi0, lagged fields, snapshot).
-static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '1'};
+static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '2'};
 
 static size_t domain_slice_bytes(const tpf_ctx* c, const HostDomain& h) {
     return domain_bytes(h, c->precision);
@@ -851,23 +857,56 @@ extern "C" int tpf_load(tpf_ctx* c, const char* path) {
     if (!c->finalized) return TPF_ESTATE;
     FILE* fp = std::fopen(path, "rb");
     if (!fp) return TPF_EIO;
+    // Pass 1 validates the whole file before any device memory changes: the
+    // header, every domain's full parameter set against the context's, and
+    // the presence of every data block (skipped with fseek).
     char magic[8];
     int32_t hdr[3];
-    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
-              std::fread(hdr, sizeof(hdr), 1, fp) == 1 && hdr[0] == c->precision &&
-              hdr[1] == (int32_t)c->doms.size() && hdr[2] == (int32_t)sizeof(tpf_domain_params);
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::fread(hdr, sizeof(hdr), 1, fp) == 1;
+    if (!ok) {
+        std::fclose(fp);
+        return TPF_EIO;
+    }
+    if (std::memcmp(magic, kMagic, 8) != 0 || hdr[0] != c->precision || hdr[1] != (int32_t)c->doms.size() ||
+        hdr[2] != (int32_t)sizeof(tpf_domain_params)) {
+        std::fclose(fp);
+        return TPF_EINVAL;
+    }
+    const long data_start = std::ftell(fp);
+    const size_t meta_bytes = 3 * sizeof(int64_t) + 2 * sizeof(double) + sizeof(int32_t);
     for (auto& h : c->doms) {
-        if (!ok) break;
+        tpf_domain_params p;
+        if (std::fread(&p, sizeof(p), 1, fp) != 1) {
+            std::fclose(fp);
+            return TPF_EIO;
+        }
+        if (std::memcmp(&p, &h.p, sizeof(p)) != 0) {
+            std::fclose(fp);
+            return TPF_EINVAL;
+        }
+        const size_t skip = meta_bytes + domain_slice_bytes(c, h);
+        // the last byte of the block must be readable
+        if (std::fseek(fp, (long)skip - 1, SEEK_CUR) != 0 || std::fgetc(fp) == EOF) {
+            std::fclose(fp);
+            return TPF_EIO;
+        }
+    }
+    // Pass 2 reads and uploads domain by domain.
+    if (std::fseek(fp, data_start, SEEK_SET) != 0) {
+        std::fclose(fp);
+        return TPF_EIO;
+    }
+    for (auto& h : c->doms) {
         tpf_domain_params p;
         int64_t meta_i[3];
         double meta_d[2];
         int32_t par;
         const size_t b = domain_slice_bytes(c, h);
         std::vector<char> buf(b);
-        ok = std::fread(&p, sizeof(p), 1, fp) == 1 && p.nx == h.p.nx && p.ny == h.p.ny &&
-             std::fread(meta_i, sizeof(meta_i), 1, fp) == 1 && std::fread(meta_d, sizeof(meta_d), 1, fp) == 1 &&
-             std::fread(&par, 4, 1, fp) == 1 && std::fread(buf.data(), 1, b, fp) == b;
-        if (!ok) break;
+        ok = std::fread(&p, sizeof(p), 1, fp) == 1 && std::fread(meta_i, sizeof(meta_i), 1, fp) == 1 &&
+             std::fread(meta_d, sizeof(meta_d), 1, fp) == 1 && std::fread(&par, 4, 1, fp) == 1 &&
+             std::fread(buf.data(), 1, b, fp) == b;
+        if (!ok) break;  // only if the file changed between the passes
         if (hipMemcpyAsync(h.dev.f[0], buf.data(), b, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
             std::fclose(fp);

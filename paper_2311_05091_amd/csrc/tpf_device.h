@@ -75,6 +75,8 @@ struct KConst {
     T sg0, sg1, sg3, sg4;        // NS rates (s2a, s2b per node)
     T inv_cfa, inv_cfb;          // 2/(1 - c_s^2) and 1/c_s^2
     T Fbx, Fby, uwx, uwy, gauge;
+    T om, xc, yc;                // solid rotation rate and centre: u_w = (uwx - om (y - yc),
+                                 //                                       uwy + om (x - xc))
     T pfac, pw, Kp, AH, BH;      // p = pfac [ sum_{i>0} g_i + (1/2 + H) Q - pw B + Kp/2 dB ],
                                  // H = Kp (AH - BH/s2a)
 };

@@ -36,7 +36,7 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // offset, so stores use scalar-base addressing.
 template <typename T, int MODE>
 __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K, bool dS, int64_t row, uint32_t cb,
-                                            int N, T ph0, T ph1,
+                                            int N, int x, int y, T ph0, T ph1,
                                             T gx0, T gy0, T lap0, T gx1, T gy1, T lap1, T mub,
                                             T gmx, T gmy, T dpsix, T dpsiy, T (&fp)[9], T (&gq)[9],
                                             T lAx, T lAy, T lB, T lCxx, T lCyy, T lCxy, int cur,
@@ -77,7 +77,10 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
     const T inv_rho = fdiv(T(1), rho);
     const T usx = (mg[1] + T(0.5) * Fx) * inv_rho;
     const T usy = (mg[2] + T(0.5) * Fy) * inv_rho;
-    const T fsx = K.uwx - usx, fsy = K.uwy - usy;
+    // rigid-body velocity of the solid point: translation plus rotation
+    const T uwx = K.uwx - K.om * (T(y) - K.yc);
+    const T uwy = K.uwy + K.om * (T(x) - K.xc);
+    const T fsx = uwx - usx, fsy = uwy - usy;
     const T ux = usx + T(0.5) * ph0 * fsx;
     const T uy = usy + T(0.5) * ph0 * fsy;
 
@@ -275,7 +278,7 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         T fp[9], gq[9];
         pull9(gin, x, y, nx, ny, px, py, N, gq);
         pull9(fin, x, y, nx, ny, px, py, N, fp);
-        node_update<T, MODE>(d, K, dS, 0, (uint32_t)id * (uint32_t)sizeof(T), N, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
+        node_update<T, MODE>(d, K, dS, 0, (uint32_t)id * (uint32_t)sizeof(T), N, x, y, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
                              s_mub[iv], gmx, gmy, dpx, dpy, fp, gq, lagA[id], lagA[N + id], lagB[id],
                              lCxx, lCyy, lCxy, cur, mom_out);
     }
@@ -535,7 +538,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
                 dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
         }
-        node_update<T, MODE>(d, K, dS, rowu, cu, N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
+        node_update<T, MODE>(d, K, dS, rowu, cu, N, x, yu, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j], gmx,
                              gmy, dpx, dpy, fU, gpl, lAx, lAy, lB, lCxx, lCyy, lCxy, cur, mom_out);
     }
 }
@@ -872,7 +875,7 @@ __device__ __forceinline__ void strip2_iter(const DomDev& d, const KConst<T>& K,
                 dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
             }
         }
-        node_update<T, MODE>(d, K, dS, (int64_t)yu * nx, (uint32_t)x * (uint32_t)sizeof(T), N, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
+        node_update<T, MODE>(d, K, dS, (int64_t)yu * nx, (uint32_t)x * (uint32_t)sizeof(T), N, x, yu, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
                              gmx, gmy, dpx, dpy, fU, gU.g, gU.lAx, gU.lAy, gU.lB, gU.lCxx, gU.lCyy, gU.lCxy,
                              cur, mom_out);
     }

@@ -39,6 +39,7 @@ class DomainParams(C.Structure):
         ("M_cst", C.c_double), ("M_deg", C.c_double), ("tau_phi", C.c_double),
         ("s_phi", C.c_double * 4), ("s_g", C.c_double * 4),
         ("Fb", C.c_double * 2), ("u_wall", C.c_double * 2),
+        ("omega_wall", C.c_double), ("wall_center", C.c_double * 2),
         ("rho_gauge", C.c_double),
     ]
 
@@ -165,6 +166,8 @@ def params_from_spec(spec: DomainSpec) -> DomainParams:
     p.s_g[:] = list(spec.s_g)
     p.Fb[:] = list(spec.Fb)
     p.u_wall[:] = list(spec.u_wall)
+    p.omega_wall = spec.omega_wall
+    p.wall_center[:] = list(spec.wall_center)
     p.rho_gauge = spec.rho_gauge
     return p
 

@@ -52,6 +52,55 @@ CASES = [
 ]
 
 
+def _slab_ratio10_accelerated():
+    """Slabs of fluid 1 in fluid 2 (density ratio 10, relaxing from twice the
+    equilibrium width) under a body force along a diagonal: the phases
+    accelerate differently, so u.grad(rho), S, F_c and the time-lagged terms
+    are all active with u != 0."""
+    nx, ny, D = 96, 21, 4.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    s = x - 0.3 * y
+    phi1 = 0.5 * (np.tanh((s - 24) / D) - np.tanh((s - 60) / D))
+    return G.DomainSpec(nx=nx, ny=ny, phi0=np.zeros((ny, nx)), phi1=phi1, periodic_x=1, periodic_y=1, D=D,
+                        theta_deg=90.0, rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015), M_cst=0.01, M_deg=0.0,
+                        Fb=(2e-5, 1e-5))
+
+
+def _diffuse_channel(uw=(0.0, 0.0), Fb=(1e-5, 0.0), periodic_y=1, ny=48, nx=67):
+    """Flow between the faces of a diffuse solid slab (rows 4-16), with a
+    droplet of fluid 1 at density ratio 10 in the channel."""
+    D = 4.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    ph0 = 0.5 * (np.tanh(2 * (y - 4) / D) - np.tanh(2 * (y - 16) / D))
+    r = np.hypot(x - nx / 2, y - 31)
+    ph1 = (1 - ph0) * (0.5 + 0.5 * np.tanh((8 - r) / (D / 2)))
+    return G.DomainSpec(nx=nx, ny=ny, phi0=ph0, phi1=ph1, periodic_x=1, periodic_y=periodic_y, D=D,
+                        theta_deg=70.0, rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015), M_deg=0.01, Fb=Fb,
+                        u_wall=uw)
+
+
+def _spinning_ring():
+    """A diffuse solid ring spinning about its centre (walls on all sides),
+    with a droplet inside at density ratio 10."""
+    n, D = 72, 4.0
+    c = n / 2 - 0.5
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    r = np.hypot(x - c, y - c)
+    ph0 = 0.5 * (np.tanh(2 * (r - 22) / D) - np.tanh(2 * (r - 30) / D))
+    ph1 = (1 - ph0) * (0.5 + 0.5 * np.tanh((7 - np.hypot(x - c - 6, y - c)) / (D / 2)))
+    return G.DomainSpec(nx=n, ny=n, phi0=ph0, phi1=ph1, periodic_x=0, periodic_y=0, D=D, theta_deg=120.0,
+                        rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015), M_deg=0.01, omega_wall=1e-3,
+                        wall_center=(c, c), u_wall=(2e-4, -1e-4))
+
+
+CASES += [
+    ("slab_ratio10_accelerated", _slab_ratio10_accelerated, 300),
+    ("diffuse_channel_ratio10", _diffuse_channel, 300),
+    ("sliding_slab_walls", lambda: _diffuse_channel(uw=(3e-3, 0.0), Fb=(0.0, 0.0), periodic_y=0), 300),
+    ("spinning_ring", _spinning_ring, 300),
+]
+
+
 @pytest.mark.parametrize("name,factory,steps", CASES, ids=[c[0] for c in CASES])
 def test_fp64_parity(orc, name, factory, steps):
     sp = factory()

@@ -71,6 +71,46 @@ def test_restart_bitwise():
     b.close()
 
 
+def test_load_rejects_other_parameters_and_truncated_files():
+    """A checkpoint of domains with another contact angle, or a truncated one,
+    is refused (TPF_EINVAL, TPF_EIO) and leaves the context's state as it was."""
+    from paper_2311_05091_amd.lbm import TpfError, TPF_EINVAL, TPF_EIO
+    specs = _mixed_batch()[:2]
+    _say("load rejection")
+    a = gpu_context(specs, precision=32)
+    a.step(50)
+    other = [G.with_params(specs[0], theta_deg=specs[0].theta_deg + 1.0), specs[1]]
+    b = gpu_context(other, precision=32)
+    b.step(20)
+    before = [b.populations(i) for i in range(2)]
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "ck.bin")
+        a.save(path)
+        with pytest.raises(TpfError) as e:
+            b.load(path)
+        assert e.value.status == TPF_EINVAL
+        c = gpu_context(specs, precision=32)
+        c.step(20)
+        before_c = [c.populations(i) for i in range(2)]
+        data = open(path, "rb").read()
+        short = os.path.join(td, "short.bin")
+        open(short, "wb").write(data[:len(data) - 100])
+        with pytest.raises(TpfError) as e:
+            c.load(short)
+        assert e.value.status == TPF_EIO
+        for i in range(2):
+            x, y = c.populations(i), before_c[i]
+            assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+        c.load(path)
+        assert c.diag(0)["steps"] == 50
+        c.close()
+    for i in range(2):
+        x, y = b.populations(i), before[i]
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    a.close()
+    b.close()
+
+
 def test_deterministic_replay():
     """Two identical runs give identical bits (no races in the LDS staging)."""
     sp = G.solid_disk_box(n=200, ny=120, Rs=20, R0=25, periodic_y=0, rho=(1.0, 1.0, 0.1),
