@@ -86,6 +86,23 @@ int tpfnn_head(const uint16_t* x, int64_t npix, int32_t C, const float* w, const
                float* pred, const float* target, uint16_t* dx, float* dw, float* db, double* loss,
                void* work, size_t work_bytes, void* stream);
 
+/* Allocation-free variant of tpfnn_head, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and results, with the partial sums
+ * in a fixed device array of TPFNN_HEAD_SCRATCH_BYTES that the library holds
+ * on each device it runs on until the process ends.  Calls with
+ * tpfnn_head_workspace(npix, C) > TPFNN_HEAD_SCRATCH_BYTES (with C = 32 about
+ * 3.9 M pixels) return TPF_EINVAL (-1) without launching anything; -2 if the
+ * array's device address cannot be obtained.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  The device current
+ * on the calling thread must be the one `stream` belongs to.  All calls on a
+ * device share its array: calls that overlap in time on one device (other
+ * streams, other threads) race and must be serialised by the caller. */
+#define TPFNN_HEAD_SCRATCH_BYTES (4u << 20)
+int tpfnn_head_noalloc(const uint16_t* x, int64_t npix, int32_t C, const float* w, const float* b,
+                       float* pred, const float* target, uint16_t* dx, float* dw, float* db, double* loss,
+                       void* stream);
+
 /* Adam with bias correction on FP32 master weights; also writes the bf16 copy
  * (p_bf16 may be NULL).  t is the 1-based step count. */
 int tpfnn_adam(float* p, float* m, float* v, const float* g, uint16_t* p_bf16, int64_t n, float lr,

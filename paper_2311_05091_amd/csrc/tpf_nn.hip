@@ -15,6 +15,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 #include "tpf_nn.h"
 
@@ -1036,4 +1037,48 @@ extern "C" int tpfnn_pack_input(const float* phi0, const float* phi1_init, const
     hipLaunchKernelGGL(pack_input_k, grid1(n), dim3(256), 0, (hipStream_t)stream, phi0, phi1_init, theta_deg,
                        vol, N, H * W, x);
     return launch_status();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of the output head.  Its per-block partial sums live
+// in a file-scope device array instead of a caller workspace.  Every device the
+// library runs on holds one copy of the array until the process ends; its
+// address on a device comes from hipGetSymbolAddress with that device current
+// (in host code the array's name is not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TPFNN_HEAD_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_on_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return kEdevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return kEdevice;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return kOk;
+}
+}  // namespace
+
+extern "C" int tpfnn_head_noalloc(const uint16_t* x, int64_t npix, int32_t C, const float* w, const float* b,
+                                  float* pred, const float* target, uint16_t* dx, float* dw, float* db,
+                                  double* loss, void* stream) {
+    if (!x || !w || !b || !pred || npix <= 0 || C <= 0 || C > 32) return kEinval;
+    if (target && (!dx || !dw || !db || !loss)) return kEinval;
+    if (tpfnn_head_workspace(npix, C) > (size_t)TPFNN_HEAD_SCRATCH_BYTES) return kEinval;
+    void* work = nullptr;
+    const int rc = scratch_on_current_device(&work);
+    if (rc != kOk) return rc;
+    // every block writes its own partial sums before the final kernel reads
+    // them, so nothing needs clearing between calls
+    return tpfnn_head(x, npix, C, w, b, pred, target, dx, dw, db, loss, work, (size_t)TPFNN_HEAD_SCRATCH_BYTES,
+                      stream);
 }

@@ -61,6 +61,7 @@ def nnlib() -> C.CDLL:
         "tpfnn_split": [V, I32, I32, I64, V, V, V],
         "tpfnn_add_inplace": [V, V, I64, V],
         "tpfnn_head": [V, I64, I32, V, V, V, V, V, V, V, V, V, C.c_size_t, V],
+        "tpfnn_head_noalloc": [V, I64, I32, V, V, V, V, V, V, V, V, V],
         "tpfnn_adam": [V, V, V, V, V, I64, F32, F32, F32, F32, I32, V],
         "tpfnn_to_bf16": [V, V, I64, V],
         "tpfnn_from_bf16": [V, V, I64, V],
@@ -85,8 +86,8 @@ def nnlib() -> C.CDLL:
 EXPORTED_NN = ("tpfnn_mfma_selftest", "tpfnn_conv3x3_fwd", "tpfnn_weight_flip", "tpfnn_wgrad_workspace",
                "tpfnn_conv3x3_wgrad", "tpfnn_relu_bwd", "tpfnn_avgpool2_fwd", "tpfnn_avgpool2_bwd",
                "tpfnn_upsample2_fwd", "tpfnn_upsample2_bwd", "tpfnn_concat", "tpfnn_split",
-               "tpfnn_add_inplace", "tpfnn_head_workspace", "tpfnn_head", "tpfnn_adam", "tpfnn_to_bf16",
-               "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input", "tpfnn_mass_project",
+               "tpfnn_add_inplace", "tpfnn_head_workspace", "tpfnn_head", "tpfnn_head_noalloc", "tpfnn_adam",
+               "tpfnn_to_bf16", "tpfnn_from_bf16", "tpfnn_resample", "tpfnn_pack_input", "tpfnn_mass_project",
                "tpfnn_mass_project_batch")
 
 
