@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpf_oracle.c")
+_SRC3 = os.path.join(_HERE, "tpf_oracle3d.c")
 _LIB_PATH = os.path.join(_HERE, "libtpf_oracle.so")
 _lib = None
 
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC3, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -56,6 +57,21 @@ class Derived(C.Structure):
         ("k", C.c_double), ("sigma01", C.c_double), ("sigma02", C.c_double),
         ("gamma", C.c_double * 3), ("gammaT", C.c_double), ("eta", C.c_double),
         ("cs2", C.c_double), ("w", C.c_double * 9), ("Kp", C.c_double),
+    ]
+
+
+class Params3(C.Structure):
+    """Parameters of a 3D domain, field for field the oracle's ``orc3_params``."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("periodic", C.c_int32 * 3),
+        ("d0", C.c_double), ("D", C.c_double), ("sigma12", C.c_double),
+        ("theta", C.c_double), ("kappa", C.c_double),
+        ("rho", C.c_double * 3), ("mu", C.c_double * 3),
+        ("M_cst", C.c_double), ("M_deg", C.c_double), ("tau_phi", C.c_double),
+        ("s_phi", C.c_double * 4), ("s_g", C.c_double * 4),
+        ("Fb", C.c_double * 3), ("u_wall", C.c_double * 3),
+        ("rho_gauge", C.c_double),
     ]
 
 
@@ -106,6 +122,35 @@ def _lib_handle():
         lib.orc_visc_rate.restype = C.c_double
         lib.orc_visc_rate.argtypes = [C.c_double] * 4
         lib.orc_num_threads.restype = C.c_int
+        if hasattr(lib, "orc3_create"):
+            lib.orc3_create.restype = C.c_void_p
+            lib.orc3_create.argtypes = [C.POINTER(Params3), _D, _D]
+            lib.orc3_free.argtypes = [C.c_void_p]
+            lib.orc3_step.argtypes = [C.c_void_p, C.c_int64]
+            lib.orc3_moments.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
+            lib.orc3_aux.argtypes = [C.c_void_p, _D, _D]
+            lib.orc3_mass.restype = C.c_double
+            lib.orc3_mass.argtypes = [C.c_void_p]
+            lib.orc3_step_count.restype = C.c_int64
+            lib.orc3_step_count.argtypes = [C.c_void_p]
+            lib.orc3_get_state.argtypes = [C.c_void_p, _D, _D, _D]
+            lib.orc3_set_state.argtypes = [C.c_void_p, _D, _D, _D]
+            lib.orc3_derived.argtypes = [C.c_void_p, _D, _D, _D]
+            lib.orc3_weights.argtypes = [C.c_double, _D]
+            lib.orc3_velocities.argtypes = [C.POINTER(C.c_int32)]
+            lib.orc3_M0.argtypes = [_D]
+            lib.orc3_N.argtypes = [C.c_double, _D]
+            lib.orc3_inverse.restype = C.c_int
+            lib.orc3_inverse.argtypes = [C.c_int, _D, _D]
+            lib.orc3_relaxation_matrix.argtypes = [C.c_double, _D, _D]
+            lib.orc3_collide.argtypes = [C.c_double, _D, _D, _D, _D, _D]
+            lib.orc3_feq.argtypes = [C.c_double, C.c_double, C.c_double, _D, _D]
+            lib.orc3_Rpop.argtypes = [C.c_double, _D, C.c_double, _D, _D]
+            lib.orc3_geq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _D, _D, _D]
+            lib.orc3_Fpop.argtypes = [C.c_double, C.c_double, _D, _D, _D]
+            lib.orc3_pressure.restype = C.c_double
+            lib.orc3_pressure.argtypes = [C.c_double, C.c_double, C.c_double, _D, C.c_double, C.c_double,
+                                          C.c_double]
         _lib = lib
     return _lib
 
@@ -322,3 +367,157 @@ class Sim:
         _lib_handle().orc_get_derived(self._h, C.byref(d))
         return {"k": d.k, "gamma": list(d.gamma), "gammaT": d.gammaT, "eta": d.eta,
                 "cs2": d.cs2, "w": list(d.w), "Kp": d.Kp}
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional (D3Q15) oracle
+# ---------------------------------------------------------------------------
+def make_params3(nx, ny, nz, *, periodic=(1, 1, 0), d0=0.5, D=4.0, sigma12=0.01, theta_deg=60.0,
+                 kappa=0.0, rho=(1.0, 1.0, 1.0), mu=(0.15, 0.15, 0.15), M_cst=0.0, M_deg=0.004,
+                 tau_phi=0.8, s_phi=(1.0, 1.0, 1.0, 1.0), s_g=(1.0, 1.0, 1.0, 1.0), Fb=(0.0, 0.0, 0.0),
+                 u_wall=(0.0, 0.0, 0.0), rho_gauge=0.0) -> Params3:
+    p = Params3()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.periodic[:] = list(periodic)
+    p.d0, p.D, p.sigma12 = d0, D, sigma12
+    p.theta, p.kappa = math.radians(theta_deg), kappa
+    p.rho[:] = list(rho)
+    p.mu[:] = list(mu)
+    p.M_cst, p.M_deg, p.tau_phi = M_cst, M_deg, tau_phi
+    p.s_phi[:] = list(s_phi)
+    p.s_g[:] = list(s_g)
+    p.Fb[:] = list(Fb)
+    p.u_wall[:] = list(u_wall)
+    p.rho_gauge = rho_gauge
+    return p
+
+
+def weights3(d0):
+    w = np.zeros(15)
+    _lib_handle().orc3_weights(d0, _ptr(w))
+    return w
+
+
+def velocities3():
+    c = (C.c_int32 * 45)()
+    _lib_handle().orc3_velocities(c)
+    return np.array(list(c)).reshape(15, 3)
+
+
+def M0_3():
+    m = np.zeros((15, 15))
+    _lib_handle().orc3_M0(_ptr(m))
+    return m
+
+
+def N3(cs2):
+    m = np.zeros((15, 15))
+    _lib_handle().orc3_N(cs2, _ptr(m))
+    return m
+
+
+def relaxation_matrix3(cs2, Kdiag):
+    S = np.zeros((15, 15))
+    _lib_handle().orc3_relaxation_matrix(cs2, _ptr(_arr(Kdiag, 15)), _ptr(S))
+    return S
+
+
+def collide3(cs2, Kdiag, f, feq, R):
+    out = np.zeros(15)
+    _lib_handle().orc3_collide(cs2, _ptr(_arr(Kdiag, 15)), _ptr(_arr(f, 15)), _ptr(_arr(feq, 15)),
+                               _ptr(_arr(R, 15)), _ptr(out))
+    return out
+
+
+def feq3(d0, phi, eta_mub, A):
+    out = np.zeros(15)
+    _lib_handle().orc3_feq(d0, phi, eta_mub, _ptr(_arr(A, 3)), _ptr(out))
+    return out
+
+
+def Rpop3(d0, dA, a, eta_g):
+    out = np.zeros(15)
+    _lib_handle().orc3_Rpop(d0, _ptr(_arr(dA, 3)), a, _ptr(_arr(eta_g, 3)), _ptr(out))
+    return out
+
+
+def geq3(d0, gauge, P, rho, u, S):
+    out = np.zeros(15)
+    _lib_handle().orc3_geq(d0, gauge, P, rho, _ptr(_arr(u, 3)), _ptr(_arr(S, 3)), _ptr(out))
+    return out
+
+
+def Fpop3(d0, Q, G, M2):
+    """M2 = (xx, yy, zz, xy, yz, xz)."""
+    out = np.zeros(15)
+    _lib_handle().orc3_Fpop(d0, Q, _ptr(_arr(G, 3)), _ptr(_arr(M2, 6)), _ptr(out))
+    return out
+
+
+def pressure3(d0, s0, s2a, g, Q, B, B_prev):
+    return _lib_handle().orc3_pressure(d0, s0, s2a, _ptr(_arr(g, 15)), Q, B, B_prev)
+
+
+class Sim3:
+    """One 3D domain advanced by the oracle.  Arrays are [nz, ny, nx], x fastest."""
+
+    NLAG = 13  # phi1 u (3), (rho u - S).u, sym(S u) (xx, yy, zz, xy, yz, xz), S x u (3)
+
+    def __init__(self, params: Params3, phi0, phi1):
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        n = params.nx * params.ny * params.nz
+        self._phi0 = _arr(phi0, n)
+        self._phi1 = _arr(phi1, n)
+        self._h = _lib_handle().orc3_create(C.byref(params), _ptr(self._phi0), _ptr(self._phi1))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib_handle().orc3_free(h)
+            self._h = None
+
+    def step(self, nsteps: int = 1):
+        _lib_handle().orc3_step(self._h, int(nsteps))
+
+    @property
+    def steps(self) -> int:
+        return _lib_handle().orc3_step_count(self._h)
+
+    def moments(self):
+        out = [np.zeros(self.shape) for _ in range(5)]
+        _lib_handle().orc3_moments(self._h, *[_ptr(a) for a in out])
+        return tuple(out)  # phi1, ux, uy, uz, p
+
+    def aux(self):
+        mub = np.zeros(self.shape)
+        gm = np.zeros((3,) + self.shape)
+        _lib_handle().orc3_aux(self._h, _ptr(mub), _ptr(gm))
+        return mub, gm
+
+    def mass(self) -> float:
+        return _lib_handle().orc3_mass(self._h)
+
+    def get_state(self):
+        f = np.zeros((15,) + self.shape)
+        g = np.zeros((15,) + self.shape)
+        lag = np.zeros((self.NLAG,) + self.shape)
+        _lib_handle().orc3_get_state(self._h, _ptr(f), _ptr(g), _ptr(lag))
+        return f, g, lag
+
+    def set_state(self, f=None, g=None, lag=None):
+        n = int(np.prod(self.shape))
+        null = C.cast(None, _D)
+        fa = _arr(f, 15 * n) if f is not None else None
+        ga = _arr(g, 15 * n) if g is not None else None
+        la = _arr(lag, self.NLAG * n) if lag is not None else None
+        _lib_handle().orc3_set_state(self._h, _ptr(fa) if fa is not None else null,
+                                     _ptr(ga) if ga is not None else null, _ptr(la) if la is not None else null)
+
+    def derived(self) -> dict:
+        k, eta = C.c_double(), C.c_double()
+        g = np.zeros(3)
+        _lib_handle().orc3_derived(self._h, C.byref(k), _ptr(g), C.byref(eta))
+        return {"k": k.value, "gamma": list(g), "eta": eta.value}

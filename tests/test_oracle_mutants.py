@@ -1,6 +1,7 @@
 """The oracle's pins catch plausible mistakes in the terms they pin.
 
-Each case plants one mistake in a copy of oracle/tpf_oracle.c (a text
+Each case plants one mistake in a copy of oracle/tpf_oracle.c or
+oracle/tpf_oracle3d.c (a text
 substitution: a dropped term, a flipped sign, a wrong factor), compiles it with
 gcc into a temporary library and runs the pin that must catch it, in a
 subprocess that loads the mutant (TPF_ORACLE_LIB).  The pin must fail.  A
@@ -15,11 +16,15 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tpf_oracle.c")
+SRC3 = os.path.join(ROOT, "oracle", "tpf_oracle3d.c")
 NORMAL = "tests/test_oracle_consistency.py::test_translating_interface_density_ratio_10"
 TANGENT = "tests/test_oracle_consistency.py::test_tangential_flow_along_relaxing_interface"
 CHANNEL = "tests/test_oracle_solid.py::test_diffuse_channel_momentum_balance"
 SLIDE = "tests/test_oracle_solid.py::test_sliding_solid_adds_its_velocity"
 SPIN = "tests/test_oracle_solid.py::test_spinning_cavity_rigid_rotation"
+NORMAL3 = "tests/test_oracle3d.py::test_translating_interface_3d_density_ratio_10"
+TANGENT3 = "tests/test_oracle3d.py::test_tangential_flow_along_relaxing_interface_3d"
+LAPLACE3 = "tests/test_oracle3d.py::test_laplace_law_sphere"
 
 # name, original text (must occur exactly once), replacement, pin that must fail
 MUTANTS = [
@@ -49,13 +54,29 @@ MUTANTS = [
     ("rotation_sign", "double uwy = P->u_wall[1] + P->omega_wall", "double uwy = P->u_wall[1] - P->omega_wall", SPIN),
 ]
 
+# mistakes planted in the three-dimensional oracle
+_FC3 = ("F[0] += -0.5 * (dpz[1] - dpy[2]);\n                F[1] += -0.5 * (dpx[2] - dpz[0]);\n"
+        "                F[2] += -0.5 * (dpy[0] - dpx[1]);")
+MUTANTS3 = [
+    ("3d_Fc_sign", _FC3, _FC3.replace("-0.5", "0.5"), TANGENT3),
+    ("3d_geq_no_S_in_shear_flux", "Pi[5] = rho * u[0] * u[2] - 0.5 * (S[0] * u[2] + u[0] * S[2]);",
+     "Pi[5] = rho * u[0] * u[2];", TANGENT3),
+    ("3d_S_sign", "S[k] = (rho1 - rho2) * Mob / s->gamma[1] * gm[k];",
+     "S[k] = -(rho1 - rho2) * Mob / s->gamma[1] * gm[k];", TANGENT3),
+    ("3d_pressure_K_of_2d", "double K = 1.0 - 2.0 * d0;", "double K = 1.0 - d0;", NORMAL3),
+    ("3d_pressure_H_of_2d", "double cH = K * (3.0 - 7.0 * d0);", "double cH = K * (2.0 - 4.0 * d0);", NORMAL3),
+    ("3d_stencil_weights", "orc3_weights(1.0 / 3.0, s->ws);", "orc3_weights(0.5, s->ws);", LAPLACE3),
+]
 
-def _run_pin(tmp_path, name, src_text, pin):
+
+def _run_pin(tmp_path, name, src_text, pin, src3_text=None):
     c = tmp_path / (name + ".c")
+    c3 = tmp_path / (name + "_3d.c")
     so = tmp_path / (name + ".so")
     c.write_text(src_text)
+    c3.write_text(src3_text if src3_text is not None else open(SRC3).read())
     subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c),
-                           "-lm"])
+                           str(c3), "-lm"])
     env = dict(os.environ, TPF_ORACLE_LIB=str(so))
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
@@ -71,4 +92,12 @@ def test_mutant_fails_its_pin(tmp_path, name, orig, repl, pin):
     src = open(SRC).read()
     assert src.count(orig) == 1, "mutation site changed: " + orig
     r = _run_pin(tmp_path, name, src.replace(orig, repl), pin)
+    assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
+
+
+@pytest.mark.parametrize("name,orig,repl,pin", MUTANTS3, ids=[m[0] for m in MUTANTS3])
+def test_mutant_3d_fails_its_pin(tmp_path, name, orig, repl, pin):
+    src3 = open(SRC3).read()
+    assert src3.count(orig) == 1, "mutation site changed: " + orig
+    r = _run_pin(tmp_path, name, open(SRC).read(), pin, src3.replace(orig, repl))
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
