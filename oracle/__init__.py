@@ -376,6 +376,8 @@ def make_params3(nx, ny, nz, *, periodic=(1, 1, 0), d0=0.5, D=4.0, sigma12=0.01,
                  kappa=0.0, rho=(1.0, 1.0, 1.0), mu=(0.15, 0.15, 0.15), M_cst=0.0, M_deg=0.004,
                  tau_phi=0.8, s_phi=(1.0, 1.0, 1.0, 1.0), s_g=(1.0, 1.0, 1.0, 1.0), Fb=(0.0, 0.0, 0.0),
                  u_wall=(0.0, 0.0, 0.0), rho_gauge=0.0) -> Params3:
+    """3D parameters; the defaults are plain values for the pins (the 3D
+    workloads pass NS s3 = s4 = 1/2 and d0 = 0.4 explicitly)."""
     p = Params3()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.periodic[:] = list(periodic)

@@ -38,8 +38,10 @@
  *   R10 the per-node NS rates are written s = (1-phi0)/(mu/(rho c) + (1-phi0)/2),
  *       identical to the viscosity relation of Sec. 3 for phi0 < 1 and finite
  *       (s -> 0) at phi0 = 1.
- *   R11 in the 2D pressure constant H the term (2 - 4 d0)/s2a is zero when its
- *       coefficient is zero (d0 = 1/2), also at saturated solid nodes (s2a = 0).
+ *   R11 in the 2D pressure constant H the term (2 - 4 d0)/s2a is taken as zero
+ *       where its coefficient is zero (d0 = 1/2) and where s2a = 0 (a saturated
+ *       solid node, phi0 = 1: its second-order NS moments do not relax, and
+ *       the relation for p holds no finite value of the term).
  *   R19 the solid-point velocity u_w of f = (u_w - u*)/dt (Sec. 3) is that of a
  *       rigid body: u_w(x) = u_wall + omega_wall e_z x (x - wall_center), with
  *       the solid field phi0 held fixed (a solid whose shape is invariant under
@@ -337,10 +339,10 @@ double orc_pressure(double d0, double s0, double s2a, const double g[9], double 
     double w[9], cs2 = d0;
     orc_weights(d0, w);
     double K = 1.0 - d0;
-    /* the s2a coefficient (2 - 4 d0) vanishes at d0 = 1/2: the term is then zero
-     * even where s2a = 0 (saturated solid), reading R11 */
+    /* the s2a term is zero where its coefficient (2 - 4 d0) is (d0 = 1/2) and
+     * at a saturated solid node (phi0 = 1, s2a = 0), reading R11 */
     double cH = 2.0 - 4.0 * d0;
-    double H = K * ((1.0 - d0) / s0 - (cH == 0.0 ? 0.0 : cH / s2a) + (1.0 - 3.0 * d0) / 2.0);
+    double H = K * ((1.0 - d0) / s0 - ((cH == 0.0 || s2a == 0.0) ? 0.0 : cH / s2a) + (1.0 - 3.0 * d0) / 2.0);
     double sum = 0.0;
     for (int i = 1; i < 9; ++i) sum += g[i];
     return cs2 / (1.0 - w[0]) *

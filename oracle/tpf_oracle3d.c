@@ -25,7 +25,8 @@
  *       previous step's psi = S x u: F_c = -curl(psi)/2 (the 2D psi is its
  *       z component);
  *   R11' in H the s2a term is zero where its coefficient K (3 - 7 d0) is zero
- *       (K = 0 at d0 = 1/2, where H vanishes altogether).
+ *       (K = 0 at d0 = 1/2, where H vanishes altogether) and, as in 2D, where
+ *       s2a = 0 (saturated solid node, phi0 = 1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -246,7 +247,7 @@ double orc3_pressure(double d0, double s0, double s2a, const double g[Q15], doub
     orc3_weights(d0, w);
     double K = 1.0 - 2.0 * d0;
     double cH = K * (3.0 - 7.0 * d0);
-    double H = K * ((1.0 - d0) / s0 + (1.0 - 3.0 * d0)) - (cH == 0.0 ? 0.0 : cH / s2a);
+    double H = K * ((1.0 - d0) / s0 + (1.0 - 3.0 * d0)) - ((cH == 0.0 || s2a == 0.0) ? 0.0 : cH / s2a);
     double sum = 0.0;
     for (int i = 1; i < Q15; ++i) sum += g[i];
     return cs2 / (1.0 - w[0]) * (sum + (0.5 + H) * Q - w[0] * B / (1.0 - cs2) + 0.5 * K * (B - B_prev));

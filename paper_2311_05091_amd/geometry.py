@@ -279,6 +279,15 @@ def held_out_set(n_domains=1024, s=256, seed0=500000, **kw) -> List[DomainSpec]:
     return [rough_wall_droplet(s, seed0 + j, **kw) for j in range(n_domains)]
 
 
+def saturate_core(phi0: np.ndarray, phi1: np.ndarray, eps: float):
+    """phi0 rounded up to exactly 1 where 1 - phi0 < eps (a solid core as FP32
+    storage rounds it), and phi1 = (1 - phi0) x front recomputed with the same
+    front; works for 2D and 3D arrays."""
+    front = phi1 / np.maximum(1.0 - phi0, 1e-300)
+    p0 = np.where(1.0 - phi0 < eps, 1.0, phi0)
+    return p0, (1.0 - p0) * front
+
+
 def with_params(spec: DomainSpec, **changes) -> DomainSpec:
     return dataclasses.replace(spec, **changes)
 
