@@ -21,9 +21,12 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -66,6 +69,88 @@ def cpu_baseline(spec, steps: int):
             "sample": "%d FP64 steps of the full %dx%d domain (after 1 untimed step)" % (steps, spec.nx, spec.ny)}
 
 
+def cpu_baseline3(spec, steps: int):
+    """The FP64 3D oracle on the host cores: `steps` steps of a 64^3 block of
+    the same workload (the full domain would take minutes per step)."""
+    import oracle
+    oracle.build(force=False)
+    n = 64
+    phi0 = np.ascontiguousarray(spec.phi0[:n, :n, :n])
+    phi1 = np.ascontiguousarray(spec.phi1[:n, :n, :n])
+    p = oracle.make_params3(n, n, n, periodic=spec.periodic, d0=spec.d0, D=spec.D, sigma12=spec.sigma12,
+                            theta_deg=spec.theta_deg, rho=spec.rho, mu=spec.mu, M_cst=spec.M_cst,
+                            M_deg=spec.M_deg, tau_phi=spec.tau_phi, Fb=spec.Fb)
+    sim = oracle.Sim3(p, phi0, phi1)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(n ** 3 * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "%d FP64 steps of a 64^3 block of the workload (after 1 untimed step)" % steps}
+
+
+def run3d(args, copy_gbs):
+    """The 3D (D3Q15) coupled step on the porous-spheres workload."""
+    import torch
+    from paper_2311_05091_amd import geometry3d as G3
+    from paper_2311_05091_amd.lbm3 import Context3
+    spec = G3.porous_spheres(n=args.n3)
+    nodes = spec.nx * spec.ny * spec.nz
+    wname = "porous_spheres_3d_%d^3" % args.n3
+    print("[bench] workload %s, %d nodes, precision %d, solid share %.3f" %
+          (wname, nodes, args.precision, float((spec.phi0 > 0.5).mean())), flush=True)
+    ctx = Context3(precision=args.precision)
+    ctx.add_domain(spec)
+    ctx.finalize()
+    if args.tile:
+        ctx.set_tile(args.tile)
+    tx, ty, tz = ctx.tile()
+    print("[bench] tile %dx%dx%d" % (tx, ty, tz), flush=True)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    settle_steps = 0
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        ctx.step(5)
+        settle_steps += 5
+    torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.kernel_timing(False)
+    mass = ctx.mass(0)
+    print("[bench] %d steps in %.3f s, kernel avg %.4f ms over %d launches, mass %.10e" %
+          (args.steps, dt, kern_ms, launches, mass), flush=True)
+    if not math.isfinite(mass):
+        raise SystemExit("bench: the 3D state is not finite after the timed steps; no figure reported")
+    bpn = ctx.bytes_per_node(0)
+    achieved = bpn * nodes / (kern_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_node": bpn,
+            "kernel_ms": round(kern_ms, 5)}
+    if copy_gbs:
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    out = {
+        "metric": METRIC, "value": round(nodes * args.steps / dt / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "settle_s": round(settle_s, 3), "settle_steps": settle_steps,
+        "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
+        "config": {"workload": wname, "nodes": nodes, "lattice": "D3Q15 x 2 (CH + NS)", "tile": [tx, ty, tz],
+                   "precision": args.precision},
+        "roofline": roof,
+    }
+    ctx.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline: 3D oracle, %d steps" % args.cpu_steps, flush=True)
+        out["cpu_baseline"] = cpu_baseline3(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +160,7 @@ def main():
     ap.add_argument("--nx", type=int, default=4096, help="porous workload width")
     ap.add_argument("--ny", type=int, default=2048, help="porous workload height")
     ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--n3", type=int, default=256, help="edge of the 3D porous workload (--workload porous3d)")
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
     ap.add_argument("--launch-mode", type=int, default=0,
                     help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
@@ -113,6 +199,8 @@ def main():
         copy_gbs = copy_bandwidth(1 << 30, nontemporal=True) / 1e9
         print("[bench] device copy (1 GiB, non-temporal): %.1f GB/s" % copy_gbs, flush=True)
 
+    if args.workload == "porous3d":
+        return run3d(args, copy_gbs)
     specs, wname = workload(args.workload, args.nx, args.ny)
     nodes = sum(s.nx * s.ny for s in specs)
     print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)
@@ -151,6 +239,8 @@ def main():
     d = ctx.diag(0)
     print("[bench] %d steps in %.3f s, kernel avg %.4f ms over %d launches, mass %.10e" %
           (args.steps, dt, kern_ms, launches, d["mass"]), flush=True)
+    if not math.isfinite(d["mass"]):
+        raise SystemExit("bench: the state is not finite after the timed steps; no figure reported")
 
     mlups = nodes * args.steps / dt / 1e6
     bpn = ctx.bytes_per_node(0)

@@ -1,6 +1,7 @@
 """Builds the HIP libraries libtpf.so and libtpf_nn.so for gfx950 with hipcc
-(in-tree).  libtpf.so is compiled from three translation units in parallel
-(the host side and the FP32 and FP64 kernel instances) and linked."""
+(in-tree).  libtpf.so is compiled from six translation units in parallel (the
+host sides of the 2D and 3D steps and their FP32 and FP64 kernel instances)
+and linked."""
 from __future__ import annotations
 
 import os
@@ -20,7 +21,8 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 COMMON = FLAGS + ["-shared"]
-LBM_SOURCES = ("tpf_api.hip", "tpf_launch_f32.hip", "tpf_launch_f64.hip")
+LBM_SOURCES = ("tpf_api.hip", "tpf_launch_f32.hip", "tpf_launch_f64.hip", "tpf3_api.hip",
+               "tpf3_launch_f32.hip", "tpf3_launch_f64.hip")
 
 
 def _compile(sources, out, extra=()):

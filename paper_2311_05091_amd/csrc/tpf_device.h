@@ -108,6 +108,16 @@ __device__ __forceinline__ const KConst<double>& kconst<double>(const DomDev& d)
 template <>
 __device__ __forceinline__ const KConst<float>& kconst<float>(const DomDev& d) { return d.kf; }
 
+// Maps blockIdx.x to a logical tile so that each XCD (blocks are dealt to
+// the 8 XCDs round-robin) processes one contiguous band of tiles, whose
+// halos then hit in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    int q = G >> 3, r = G & 7;
+    int x = b & 7;
+    int start = x * q + (x < r ? x : r);
+    return start + (b >> 3);
+}
+
 // Window cell -> node index.  Periodic axes wrap; across a half-way wall the
 // node is the even mirror (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).  Cells
 // farther out only occur in the unused part of a ragged tile's window and

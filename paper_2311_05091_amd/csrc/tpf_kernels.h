@@ -18,16 +18,6 @@ namespace tpf {
 
 enum StepMode { kModeStep = 0, kModeMoments = 1 };
 
-// Maps blockIdx.x to a logical tile so that each XCD (blocks are dealt to
-// the 8 XCDs round-robin) processes one contiguous band of tiles, whose
-// halos then hit in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int G) {
-    int q = G >> 3, r = G & 7;
-    int x = b & 7;
-    int start = x * q + (x < r ? x : r);
-    return start + (b >> 3);
-}
-
 // Per-node part of the step, shared by the tile and strip kernels: given the
 // stencil values of phi0, phi1, mubar1 (and psi), the pulled populations and
 // the lagged fields of the node, forms the forces, u, p and writes either the
@@ -92,7 +82,9 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
     // pressure (Sec. 3, 2D constants)
     const T Q = ux * drx + uy * dry;
     const T Bn = (rho * ux - Sx) * ux + (rho * uy - Sy) * uy;
-    const T H = K.Kp * (K.AH - (d.bh_zero ? T(0) : fdiv(K.BH, s2a)));
+    // the s2a term of H is zero where its coefficient is and at a saturated
+    // solid node (phi0 = 1 in the working precision, s2a = 0)
+    const T H = K.Kp * (K.AH - ((d.bh_zero || s2a == T(0)) ? T(0) : fdiv(K.BH, s2a)));
     const T p = K.pfac * ((mg[0] - gq[0]) + (T(0.5) + H) * Q - K.pw * Bn +
                              T(0.5) * K.Kp * (Bn - lB));
 

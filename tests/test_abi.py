@@ -63,3 +63,23 @@ def test_copy_bandwidth_rejects_bad_arguments_before_any_device_work():
     assert f(16, 4096, 32, 0, 0, None, ctypes.byref(ms)) == EINVAL             # no repetition
     assert f(24, 4096, 32, 0, 1, None, ctypes.byref(ms)) == EINVAL             # misaligned source
     assert f(16, 32, 32, 0, 1, None, ctypes.byref(ms)) == EINVAL               # overlapping buffers
+
+
+def test_tpf3_exports_every_declared_symbol():
+    names = header_functions(os.path.join(ROOT, "include", "tpf3.h"))
+    assert "tpf3_step" in names and len(names) >= 12
+    lib = _lib("libtpf.so")
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_2311_05091_amd import lbm3
+    assert sorted(lbm3.EXPORTED3) == names
+
+
+def test_tpf3_default_params():
+    from paper_2311_05091_amd import lbm3
+    lib = lbm3.library3()
+    p = lbm3.DomainParams3()
+    lib.tpf3_default_params(ctypes.byref(p), 32, 24, 16)
+    assert (p.nx, p.ny, p.nz, list(p.periodic)) == (32, 24, 16, [1, 1, 0])
+    assert p.d0 == 0.4 and p.M_deg == 0.004 and p.tau_phi == 0.8
+    assert list(p.s_g) == [1.0, 1.0, 0.5, 0.5]

@@ -93,7 +93,17 @@ def _spinning_ring():
                         wall_center=(c, c), u_wall=(2e-4, -1e-4))
 
 
+def _saturated_disk():
+    """A solid disk whose core is exactly phi0 = 1 (reading R11: the s2a term of
+    H is dropped there) at d0 = 0.4 and density ratio 10."""
+    sp = G.with_params(G.solid_disk_box(n=48, Rs=14.0, R0=8.0, D=4.0, rho=(1.0, 1.0, 0.1),
+                                        mu=(0.15, 0.15, 0.015)), d0=0.4)
+    p0, p1 = G.saturate_core(sp.phi0, sp.phi1, 1e-4)
+    return G.with_params(sp, phi0=p0, phi1=p1)
+
+
 CASES += [
+    ("saturated_core_d0_04", _saturated_disk, 300),
     ("slab_ratio10_accelerated", _slab_ratio10_accelerated, 300),
     ("diffuse_channel_ratio10", _diffuse_channel, 300),
     ("sliding_slab_walls", lambda: _diffuse_channel(uw=(3e-3, 0.0), Fb=(0.0, 0.0), periodic_y=0), 300),
