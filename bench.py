@@ -161,7 +161,8 @@ def main():
     ap.add_argument("--ny", type=int, default=2048, help="porous workload height")
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--n3", type=int, default=256, help="edge of the 3D porous workload (--workload porous3d)")
-    ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune")
+    ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune (per size class for batches)")
+    ap.add_argument("--tile-cache", default=None, help="JSON cache of the per-size-class autotuner")
     ap.add_argument("--launch-mode", type=int, default=0,
                     help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
     ap.add_argument("--settle-s", type=float, default=0.3,
@@ -182,7 +183,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2311_05091_amd.lbm import Context
+    from paper_2311_05091_amd.lbm import Context, size_class
 
     if args.copy_mib > 0:
         # reference copy kernel of known size (reads and writes copy_mib MiB)
@@ -208,8 +209,17 @@ def main():
     for s in specs:
         ctx.add_domain(s)
     ctx.finalize()
+    per_class = None
     if args.tile:
         ctx.set_tile(args.tile)
+    elif len(specs) > 1 and args.launch_mode == 0:
+        # a batch of many sizes: one tile code per size class
+        ctx.autotune_classes(steps=10, cache_path=args.tile_cache)
+        per_class = {}
+        for i, sp in enumerate(specs):
+            key = size_class(args.precision, sp.nx, sp.ny, sp.rho[1] != sp.rho[2])
+            per_class.setdefault(key, [ctx.domain_tile(i), 0])[1] += 1
+        print("[bench] tile per size class (code, domains): %s" % per_class, flush=True)
     else:
         ctx.autotune(steps=30)
     code, tx, ty = ctx.tile()
@@ -259,7 +269,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
         "config": {"workload": wname, "nodes": nodes, "lattice": "D2Q9 x 2 (CH + NS)",
-                   "tile": [tx, ty], "precision": args.precision, "launch_mode": args.launch_mode},
+                   "tile": [tx, ty] if per_class is None else per_class, "precision": args.precision,
+                   "launch_mode": args.launch_mode},
         "roofline": roof,
     }
     ctx.close()

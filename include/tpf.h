@@ -158,8 +158,35 @@ int tpf_get_tile(tpf_ctx* ctx, int32_t* tile_code, int32_t* tile_x, int32_t* til
 /* Number of tile shapes and their codes/extents (arrays of n entries). */
 int tpf_tile_codes(int32_t* n, int32_t* codes, int32_t* tx, int32_t* ty);
 /* Times every tile shape on the current domains for `steps` steps each and
- * keeps the fastest; the state is restored afterwards.  best_ms may be NULL. */
+ * keeps the fastest for all of them (clearing per-domain codes); the state is
+ * restored afterwards.  best_ms may be NULL. */
 int tpf_autotune(tpf_ctx* ctx, int32_t steps, double* best_ms);
+
+/* Size class of a domain for the per-class autotuner: precision, whether it
+ * carries the flux S (rho1 != rho2), and nx, ny rounded up to powers of two,
+ * written as "p32_s0_w256_h512" into buf (len bytes, NUL-terminated).  Host
+ * only.  TPF_EINVAL for bad arguments or a short buffer. */
+int tpf_size_class(int32_t precision, int32_t nx, int32_t ny, int32_t has_s, char* buf, int32_t len);
+
+/* Per-size-class autotuning.  For every class among the domains that take
+ * part in the steps, the tile code comes from the cache file cache_path when
+ * it holds that class for this device (architecture and compute-unit count),
+ * else every tile shape is timed for `steps` steps on the class's domains
+ * alone and the fastest kept.  Each domain then runs its class's code:
+ * tpf_step launches one kernel per (code, S) group.  The state of every
+ * domain is restored.  When classes were timed and cache_path is not NULL,
+ * the cache is rewritten (its other entries kept; written to a temporary
+ * file and renamed); a file of another format or device is replaced.
+ * n_timed (may be NULL) = classes that were timed.  TPF_EINVAL in launch mode
+ * 2 (which chooses one code itself) or for steps <= 0; TPF_EIO if the cache
+ * cannot be written.  tpf_set_tile and tpf_autotune return to one code for
+ * all domains.  Cache format (JSON, one entry per line):
+ *   {"format": "tpf-autotune-1", "device": "gfx950:256", "entries": {
+ *     "p32_s0_w256_h256": {"code": 21, "ms_per_step": 0.05}, ... }} */
+int tpf_autotune_classes(tpf_ctx* ctx, int32_t steps, const char* cache_path, int32_t* n_timed);
+
+/* Tile code domain id runs in the next step. */
+int tpf_domain_tile(tpf_ctx* ctx, int32_t id, int32_t* code);
 
 /* Launch mode of tpf_step / tpf_run_to_residual: 0 = one kernel launch per
  * step over all live domains' tiles; 1 = one persistent launch per call that

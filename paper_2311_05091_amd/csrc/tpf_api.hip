@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -24,25 +25,21 @@ namespace tpf {
 struct TileShape {
     int code, tx, ty, threads;
 };
-// codes are stable across builds.  1-7: tile kernel (256 threads, whole-tile
-// LDS window); 8-11: strip kernel (one wavefront marching down a 64-column
-// strip of ty rows); 12-14: pipelined strip kernel (one wavefront per
-// 60-column strip, next row's loads in flight during the current row);
-// 15-16: strip kernel compiled for five wavefronts per SIMD; 17, 18, 20:
-// groups of 4 or 2 strip wavefronts per workgroup advancing in lockstep
-// (groups of 8 would need more than the 64 KB of LDS a workgroup may hold in
-// FP64 with the S flux); 21, 22: groups of 4 strips of 32 or 64 rows with
-// the register budget left to the compiler; 23, 24: code 22 with
-// non-temporal loads of the pulled populations of both lattices (23) or of
-// the NS lattice only (24).
-static const TileShape kTiles[] = {{1, 64, 4, 256},  {2, 64, 8, 256},   {3, 64, 16, 256},
-                                   {4, 128, 8, 256}, {5, 32, 8, 256},   {6, 64, 32, 256},
-                                   {7, 128, 16, 256}, {8, 64, 16, 64},  {9, 64, 32, 64},
-                                   {10, 64, 64, 64}, {11, 64, 128, 64}, {12, 60, 16, 64},
-                                   {13, 60, 32, 64}, {14, 60, 64, 64}, {15, 64, 32, 64},
-                                   {16, 64, 16, 64}, {17, 256, 32, 256}, {18, 128, 32, 128},
-                                   {20, 256, 16, 256}, {21, 256, 32, 256}, {22, 256, 64, 256},
-                                   {23, 256, 64, 256}, {24, 256, 64, 256}};
+// codes are stable across builds.  1, 2: tile kernel (256 threads, whole-tile
+// LDS window, 64 x 4 and 64 x 8 nodes: the small tiles of launch mode 2);
+// 8-10: strip kernel (one wavefront marching down a 64-column strip of ty
+// rows; also the persistent launch); 17, 18, 20: groups of 4 or 2 strip
+// wavefronts per workgroup advancing in lockstep (groups of 8 would need more
+// than the 64 KB of LDS a workgroup may hold in FP64 with the S flux); 21,
+// 22: groups of 4 strips of 32 or 64 rows with the register budget left to
+// the compiler; 23, 24: code 22 with non-temporal loads of the pulled
+// populations of both lattices (23) or of the NS lattice only (24).  Codes 3-7
+// and 11-16 (other tile sizes, a pipelined strip and a five-waves strip) were
+// never the fastest on any workload measured and are no longer built.
+static const TileShape kTiles[] = {{1, 64, 4, 256},   {2, 64, 8, 256},   {8, 64, 16, 64},
+                                   {9, 64, 32, 64},   {10, 64, 64, 64},  {17, 256, 32, 256},
+                                   {18, 128, 32, 128}, {20, 256, 16, 256}, {21, 256, 32, 256},
+                                   {22, 256, 64, 256}, {23, 256, 64, 256}, {24, 256, 64, 256}};
 static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 static const int kDefaultTile = 9;
 
@@ -57,6 +54,14 @@ struct HostDomain {
     int64_t snap_step = -1;
     double k = 0, gamma[3] = {0, 0, 0}, gammaT = 0, eta = 0;
     size_t off = 0, bytes = 0;  // arena slice
+    int tile = 0;               // tile code of this domain (0: the context's)
+};
+
+// A contiguous run of the tile table whose tiles share one kernel instance.
+struct TileGroup {
+    int code;
+    bool s;
+    int begin, count;
 };
 
 }  // namespace tpf
@@ -88,6 +93,7 @@ struct tpf_ctx {
     int* d_done = nullptr;       // [ndom]
     int* d_dom_tiles = nullptr;  // [ndom]
     int n_cu = 0;
+    std::string device;          // architecture name and compute units (autotune cache key)
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -96,7 +102,7 @@ struct tpf_ctx {
     int64_t t_launches = 0;
     // current tile table
     std::vector<int4> tiles;
-    int tiles_noS = 0;  // tiles of domains without S come first
+    std::vector<TileGroup> groups;  // one per (tile code, S) among the live domains
     std::vector<int> live_list;
     int tiles_code_built = -1;
     bool tiles_dirty = true;
@@ -111,6 +117,12 @@ static const TileShape* find_tile(int code) {
     for (int i = 0; i < kNumTiles; ++i)
         if (kTiles[i].code == code) return &kTiles[i];
     return nullptr;
+}
+
+// Tile code a domain runs: its own (set by the per-class autotuner) unless
+// launch mode 2 chooses one code for all.
+static int eff_code(const tpf_ctx* c, const HostDomain& h) {
+    return (c->launch_mode != 2 && h.tile) ? h.tile : c->tile_code;
 }
 
 #define HIP_OK(expr)                                  \
@@ -278,14 +290,16 @@ static size_t domain_bytes(const HostDomain& h, int prec) {
     return b;
 }
 
+// Capacity of the tile table: every domain at its own largest tile count
+// (domains may run different codes).
 static void count_tiles(const tpf_ctx* c, size_t& max_tiles) {
     max_tiles = 0;
-    for (int i = 0; i < kNumTiles; ++i) {
-        size_t t = 0;
-        for (auto& h : c->doms)
-            t += (size_t)((h.p.nx + kTiles[i].tx - 1) / kTiles[i].tx) *
-                 ((h.p.ny + kTiles[i].ty - 1) / kTiles[i].ty);
-        max_tiles = std::max(max_tiles, t);
+    for (auto& h : c->doms) {
+        size_t m = 0;
+        for (int i = 0; i < kNumTiles; ++i)
+            m = std::max(m, (size_t)((h.p.nx + kTiles[i].tx - 1) / kTiles[i].tx) *
+                                ((h.p.ny + kTiles[i].ty - 1) / kTiles[i].ty));
+        max_tiles += m;
     }
 }
 
@@ -314,16 +328,17 @@ static size_t total_bytes(tpf_ctx* c) {
 // ---------------------------------------------------------------------------
 // Launch helpers (the kernel instances live in tpf_launch_f32/f64.hip)
 // ---------------------------------------------------------------------------
-// Launches the step (or moments) kernel over a tile table whose first n_noS
-// tiles belong to domains without S and the rest to domains with S.
-static hipError_t launch_step(tpf_ctx* c, int mode, int ntiles, int n_noS, int offset, double* mom) {
+// Launches the step (or moments) kernel once per group of the tile table,
+// each with the instance of its tile code and S flag.
+static hipError_t launch_step(tpf_ctx* c, int mode, const std::vector<TileGroup>& groups, int offset,
+                              double* mom) {
     auto run = c->precision == 32 ? launch_tiles_f32 : launch_tiles_f64;
-    TileLaunch a{c->stream, c->d_doms, c->d_tiles, n_noS, offset, mom};
-    hipError_t e = run(c->tile_code, false, mode, a);
-    if (e != hipSuccess) return e;
-    a.tiles = c->d_tiles + n_noS;
-    a.ntiles = ntiles - n_noS;
-    return run(c->tile_code, true, mode, a);
+    for (const TileGroup& g : groups) {
+        TileLaunch a{c->stream, c->d_doms, c->d_tiles + g.begin, g.count, offset, mom};
+        hipError_t e = run(g.code, g.s, mode, a);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Host -> device upload of all descriptors (small; issued on the stream).
@@ -337,24 +352,27 @@ static int upload_descriptors(tpf_ctx* c) {
     return TPF_OK;
 }
 
-// Tile table for a set of domains (all live ones, or one for moments):
-// tiles of domains without the flux S first, then those with S, so each
-// group runs the kernel instance of its own kind.
+// Tile table for a set of domains (all live ones, or one for moments),
+// grouped by (tile code, S) in increasing code order, domains without the
+// flux S first within a code, so each group runs one kernel instance.
 static int build_tiles(tpf_ctx* c, const std::vector<int>& which, std::vector<int4>& out,
-                       int* n_noS = nullptr) {
-    const TileShape* ts = find_tile(c->tile_code);
+                       std::vector<TileGroup>& groups) {
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int di : which) by[{eff_code(c, c->doms[di]), c->doms[di].dev.has_s ? 1 : 0}].push_back(di);
     out.clear();
-    int split = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int di : which) {
+    groups.clear();
+    for (auto& kv : by) {
+        const TileShape* ts = find_tile(kv.first.first);
+        if (!ts) return TPF_EINVAL;
+        TileGroup g{kv.first.first, kv.first.second != 0, (int)out.size(), 0};
+        for (int di : kv.second) {
             const auto& h = c->doms[di];
-            if ((h.dev.has_s != 0) != (pass == 1)) continue;
             for (int y = 0; y < h.p.ny; y += ts->ty)
                 for (int x = 0; x < h.p.nx; x += ts->tx) out.push_back(make_int4(di, x, y, 0));
         }
-        if (pass == 0) split = (int)out.size();
+        g.count = (int)out.size() - g.begin;
+        groups.push_back(g);
     }
-    if (n_noS) *n_noS = split;
     if (out.size() > c->max_tiles) return TPF_EINVAL;
     if (!out.empty())
         HIP_OK(hipMemcpyAsync(c->d_tiles, out.data(), out.size() * sizeof(int4),
@@ -369,7 +387,7 @@ static int refresh_live(tpf_ctx* c) {
         if (stepping(c->doms[i])) live.push_back((int)i);
     if (live != c->live_list || c->tiles_dirty || c->tiles_code_built != c->tile_code) {
         c->live_list = live;
-        int rc = build_tiles(c, live, c->tiles, &c->tiles_noS);
+        int rc = build_tiles(c, live, c->tiles, c->groups);
         if (rc) return rc;
         c->tiles_code_built = c->tile_code;
         c->tiles_dirty = false;
@@ -377,8 +395,13 @@ static int refresh_live(tpf_ctx* c) {
     return TPF_OK;
 }
 
+// The persistent launch runs one strip code (8-10) for every live domain.
 static bool persistent_ok(const tpf_ctx* c) {
-    return c->launch_mode == 1 && (c->tile_code == 8 || c->tile_code == 9 || c->tile_code == 10);
+    if (c->launch_mode != 1 || c->groups.empty()) return false;
+    const int code = c->groups[0].code;
+    for (const TileGroup& g : c->groups)
+        if (g.code != code) return false;
+    return code == 8 || code == 9 || code == 10;
 }
 
 // n steps of all live domains in persistent launches (chunks fit the
@@ -389,7 +412,9 @@ static int run_persistent(tpf_ctx* c, int64_t n) {
     for (const int4& t : c->tiles) per[t.x]++;
     HIP_OK(hipMemcpyAsync(c->d_dom_tiles, per.data(), per.size() * sizeof(int), hipMemcpyHostToDevice,
                           c->stream));
-    const bool S = c->tiles_noS < ntiles;  // some live domain has S: the S-capable instance
+    bool S = false;  // some live domain has S: the S-capable instance
+    for (const TileGroup& g : c->groups) S = S || g.s;
+    const int code = c->groups[0].code;
     const int64_t max_chunk = std::max<int64_t>(2, ((int64_t)1 << 30) / std::max(ntiles, 1));
     int64_t done_steps = 0;
     while (done_steps < n) {
@@ -406,8 +431,8 @@ static int run_persistent(tpf_ctx* c, int64_t n) {
         }
         const PersistentLaunch pl{c->stream, c->d_doms, c->d_tiles, ntiles, (int)m, c->d_dom_tiles,
                                   c->d_ctl, c->d_done, c->n_cu, 1 << 22};
-        HIP_OK(c->precision == 32 ? launch_persistent_f32(c->tile_code, S, pl)
-                                  : launch_persistent_f64(c->tile_code, S, pl));
+        HIP_OK(c->precision == 32 ? launch_persistent_f32(code, S, pl)
+                                  : launch_persistent_f64(code, S, pl));
         if (c->timing) {
             HIP_OK(hipEventRecord(b, c->stream));
             c->ev_pool.push_back(a);
@@ -457,6 +482,7 @@ static void adapt_tile(tpf_ctx* c) {
             break;
         }
     }
+    if (pick != c->tile_code) c->tiles_dirty = true;
     c->tile_code = pick;
 }
 
@@ -474,8 +500,6 @@ static int run_steps(tpf_ctx* c, int64_t n) {
     rc = upload_descriptors(c);
     if (rc) return rc;
     if (persistent_ok(c)) return run_persistent(c, n);
-    const int ntiles = (int)c->tiles.size();
-    const int nnoS = c->tiles_noS;
     // timing: one event pair around the call's n back-to-back launches (an
     // event between every two launches measurably slowed the run: 282 against
     // 275 us per step on the 4096 x 2048 workload), so the average per launch
@@ -486,7 +510,7 @@ static int run_steps(tpf_ctx* c, int64_t n) {
         HIP_OK(hipEventCreate(&tb));
         HIP_OK(hipEventRecord(ta, c->stream));
     }
-    for (int64_t s = 0; s < n; ++s) HIP_OK(launch_step(c, kModeStep, ntiles, nnoS, (int)(s & 1), nullptr));
+    for (int64_t s = 0; s < n; ++s) HIP_OK(launch_step(c, kModeStep, c->groups, (int)(s & 1), nullptr));
     if (c->timing) {
         HIP_OK(hipEventRecord(tb, c->stream));
         c->ev_pool.push_back(ta);
@@ -673,6 +697,7 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
         hipDeviceProp_t prop;
         HIP_OK(hipGetDeviceProperties(&prop, dev));
         c->n_cu = prop.multiProcessorCount;
+        c->device = std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount);
     }
     int rc = upload_descriptors(c);
     if (rc) return rc;
@@ -746,12 +771,12 @@ extern "C" int tpf_read_moments(tpf_ctx* c, int32_t id, double* phi1, double* ux
     auto& h = c->doms[id];
     const size_t N = (size_t)h.p.nx * h.p.ny;
     std::vector<int4> t;
+    std::vector<TileGroup> grp;
     std::vector<int> one = {id};
-    int nnoS = 0;
-    int rc = build_tiles(c, one, t, &nnoS);
+    int rc = build_tiles(c, one, t, grp);
     if (rc) return rc;
     c->tiles_dirty = true;
-    HIP_OK(launch_step(c, kModeMoments, (int)t.size(), nnoS, 0, c->d_scratch));
+    HIP_OK(launch_step(c, kModeMoments, grp, 0, c->d_scratch));
     std::vector<double> buf(4 * N);
     HIP_OK(hipMemcpyAsync(buf.data(), c->d_scratch, 4 * N * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
@@ -938,15 +963,16 @@ extern "C" int tpf_tile_codes(int32_t* n, int32_t* codes, int32_t* tx, int32_t* 
 
 extern "C" int tpf_set_tile(tpf_ctx* c, int32_t code) {
     if (!c) return TPF_EINVAL;
+    if (code != 0 && !find_tile(code)) return TPF_EINVAL;
+    for (auto& h : c->doms) h.tile = 0;  // one code for all domains again
+    c->tiles_dirty = true;
     if (code == 0) {
         c->tile_from_user = false;
         c->tuned = false;
         return TPF_OK;
     }
-    if (!find_tile(code)) return TPF_EINVAL;
     c->tile_code = code;
     c->tile_from_user = true;
-    c->tiles_dirty = true;
     return TPF_OK;
 }
 
@@ -959,59 +985,220 @@ extern "C" int tpf_get_tile(tpf_ctx* c, int32_t* code, int32_t* tx, int32_t* ty)
     return TPF_OK;
 }
 
-extern "C" int tpf_autotune(tpf_ctx* c, int32_t steps, double* best_ms) {
-    if (!c || steps <= 0) return TPF_EINVAL;
-    if (!c->finalized) return TPF_ESTATE;
-    // save the state of every domain (device slices + bookkeeping)
-    std::vector<std::vector<char>> saved(c->doms.size());
-    std::vector<HostDomain> meta = c->doms;
+extern "C" int tpf_domain_tile(tpf_ctx* c, int32_t id, int32_t* code) {
+    if (!c || !code || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    *code = eff_code(c, c->doms[id]);
+    return TPF_OK;
+}
+
+// Device state of every domain and its bookkeeping, saved before timing runs
+// and put back afterwards.
+struct SavedState {
+    std::vector<std::vector<char>> slices;
+    std::vector<HostDomain> meta;
+};
+
+static int save_state(tpf_ctx* c, SavedState& st) {
+    st.slices.assign(c->doms.size(), {});
+    st.meta = c->doms;
     for (size_t i = 0; i < c->doms.size(); ++i) {
         const size_t b = domain_slice_bytes(c, c->doms[i]);
-        saved[i].resize(b);
-        HIP_OK(hipMemcpyAsync(saved[i].data(), c->doms[i].dev.f[0], b, hipMemcpyDeviceToHost, c->stream));
+        st.slices[i].resize(b);
+        HIP_OK(hipMemcpyAsync(st.slices[i].data(), c->doms[i].dev.f[0], b, hipMemcpyDeviceToHost, c->stream));
     }
     HIP_OK(hipStreamSynchronize(c->stream));
-    int best = c->tile_code;
-    double best_t = 1e300;
+    return TPF_OK;
+}
+
+static int restore_state(tpf_ctx* c, const SavedState& st) {
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        HIP_OK(hipMemcpyAsync(c->doms[i].dev.f[0], st.slices[i].data(), st.slices[i].size(), hipMemcpyHostToDevice,
+                              c->stream));
+        auto& h = c->doms[i];
+        const auto& m = st.meta[i];
+        h.steps = m.steps;
+        h.dev.parity = m.dev.parity;
+        h.status = m.status;
+        h.active = m.active;
+        h.residual = m.residual;
+        h.snap_step = m.snap_step;
+        h.mass = m.mass;
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->tiles_dirty = true;
+    return upload_descriptors(c);
+}
+
+// Average time per step of `steps` steps of the live domains with their
+// current codes (after two untimed steps that also build the tile table).
+static int time_steps(tpf_ctx* c, int32_t steps, double* per_step_ms) {
+    c->tiles_dirty = true;
+    int rc = run_steps(c, 2);
+    if (rc) return rc;
     hipEvent_t a, b;
     HIP_OK(hipEventCreate(&a));
     HIP_OK(hipEventCreate(&b));
+    HIP_OK(hipEventRecord(a, c->stream));
+    rc = run_steps(c, steps);
+    if (rc) return rc;
+    HIP_OK(hipEventRecord(b, c->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *per_step_ms = ms / steps;
+    return TPF_OK;
+}
+
+extern "C" int tpf_autotune(tpf_ctx* c, int32_t steps, double* best_ms) {
+    if (!c || steps <= 0) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    SavedState st;
+    int rc = save_state(c, st);
+    if (rc) return rc;
+    for (auto& h : c->doms) h.tile = 0;
+    int best = c->tile_code;
+    double best_t = 1e300;
     for (int i = 0; i < kNumTiles; ++i) {
         c->tile_code = kTiles[i].code;
-        c->tiles_dirty = true;
-        int rc = run_steps(c, 2);  // warm-up (also builds the tile table)
+        double per = 0;
+        rc = time_steps(c, steps, &per);
         if (rc) return rc;
-        HIP_OK(hipEventRecord(a, c->stream));
-        rc = run_steps(c, steps);
-        if (rc) return rc;
-        HIP_OK(hipEventRecord(b, c->stream));
-        HIP_OK(hipEventSynchronize(b));
-        float ms = 0;
-        HIP_OK(hipEventElapsedTime(&ms, a, b));
-        const double per = ms / steps;
         if (per < best_t) {
             best_t = per;
             best = kTiles[i].code;
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    for (size_t i = 0; i < c->doms.size(); ++i) {
-        HIP_OK(hipMemcpyAsync(c->doms[i].dev.f[0], saved[i].data(), saved[i].size(), hipMemcpyHostToDevice,
-                              c->stream));
-        c->doms[i].steps = meta[i].steps;
-        c->doms[i].dev.parity = meta[i].dev.parity;
-        c->doms[i].status = meta[i].status;
-        c->doms[i].residual = meta[i].residual;
-        c->doms[i].snap_step = meta[i].snap_step;
-        c->doms[i].mass = meta[i].mass;
-    }
-    HIP_OK(hipStreamSynchronize(c->stream));
     c->tile_code = best;
     c->tuned = true;
-    c->tiles_dirty = true;
     if (best_ms) *best_ms = best_t;
-    return upload_descriptors(c);
+    return restore_state(c, st);
+}
+
+// ---------------------------------------------------------------------------
+// Per-size-class autotuning with a JSON cache
+// ---------------------------------------------------------------------------
+static int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+static std::string size_class(int precision, int nx, int ny, bool has_s) {
+    char buf[64];
+    std::snprintf(buf, sizeof(buf), "p%d_s%d_w%d_h%d", precision, has_s ? 1 : 0, pow2_at_least(nx),
+                  pow2_at_least(ny));
+    return buf;
+}
+
+extern "C" int tpf_size_class(int32_t precision, int32_t nx, int32_t ny, int32_t has_s, char* buf, int32_t len) {
+    if (!buf || len <= 0 || (precision != 32 && precision != 64) || nx < 1 || ny < 1) return TPF_EINVAL;
+    const std::string k = size_class(precision, nx, ny, has_s != 0);
+    if ((int)k.size() + 1 > len) return TPF_EINVAL;
+    std::memcpy(buf, k.c_str(), k.size() + 1);
+    return TPF_OK;
+}
+
+struct CacheEntry {
+    int code;
+    double ms;
+};
+
+static const char kCacheFormat[] = "tpf-autotune-1";
+
+// Reads the entries of a cache file written by write_cache for this device;
+// a missing file, another format or another device give no entries.  Entries
+// naming a tile code this build does not have are dropped.
+static void read_cache(const char* path, const std::string& device, std::map<std::string, CacheEntry>& out) {
+    out.clear();
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    bool format_ok = false, device_ok = false;
+    std::map<std::string, CacheEntry> tmp;
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[128], val[128];
+        int code = 0;
+        double ms = 0;
+        if (std::sscanf(line, " \"format\": \"%127[^\"]\"", val) == 1) format_ok = std::strcmp(val, kCacheFormat) == 0;
+        else if (std::sscanf(line, " \"device\": \"%127[^\"]\"", val) == 1) device_ok = device == val;
+        else if (std::sscanf(line, " \"%127[^\"]\": {\"code\": %d, \"ms_per_step\": %lf}", key, &code, &ms) == 3 &&
+                 find_tile(code))
+            tmp[key] = CacheEntry{code, ms};
+    }
+    std::fclose(f);
+    if (format_ok && device_ok) out = tmp;
+}
+
+static bool write_cache(const char* path, const std::string& device, const std::map<std::string, CacheEntry>& e) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n  \"format\": \"%s\",\n  \"device\": \"%s\",\n  \"entries\": {\n", kCacheFormat,
+                 device.c_str());
+    size_t i = 0;
+    for (const auto& kv : e)
+        std::fprintf(f, "    \"%s\": {\"code\": %d, \"ms_per_step\": %.6g}%s\n", kv.first.c_str(), kv.second.code,
+                     kv.second.ms, ++i < e.size() ? "," : "");
+    std::fprintf(f, "  }\n}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+extern "C" int tpf_autotune_classes(tpf_ctx* c, int32_t steps, const char* cache_path, int32_t* n_timed) {
+    if (!c || steps <= 0) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    if (c->launch_mode == 2) return TPF_EINVAL;  // mode 2 chooses the code itself
+    // classes of the domains that take part in the steps
+    std::map<std::string, std::vector<int>> classes;
+    for (size_t i = 0; i < c->doms.size(); ++i) {
+        const auto& h = c->doms[i];
+        if (!stepping(h)) continue;
+        classes[size_class(c->precision, h.p.nx, h.p.ny, h.dev.has_s != 0)].push_back((int)i);
+    }
+    std::map<std::string, CacheEntry> cache;
+    if (cache_path) read_cache(cache_path, c->device, cache);
+    SavedState st;
+    int rc = save_state(c, st);
+    if (rc) return rc;
+    int timed = 0;
+    std::map<std::string, int> chosen;
+    for (const auto& kv : classes) {
+        auto it = cache.find(kv.first);
+        if (it != cache.end()) {
+            chosen[kv.first] = it->second.code;
+            continue;
+        }
+        // time this class alone: every other domain sits out
+        for (size_t i = 0; i < c->doms.size(); ++i) c->doms[i].active = false;
+        for (int di : kv.second) c->doms[di].active = true;
+        int best = kTiles[0].code;
+        double best_t = 1e300;
+        for (int t = 0; t < kNumTiles; ++t) {
+            for (int di : kv.second) c->doms[di].tile = kTiles[t].code;
+            double per = 0;
+            rc = time_steps(c, steps, &per);
+            if (rc) return rc;
+            if (per < best_t) {
+                best_t = per;
+                best = kTiles[t].code;
+            }
+        }
+        chosen[kv.first] = best;
+        cache[kv.first] = CacheEntry{best, best_t};
+        ++timed;
+        rc = restore_state(c, st);  // also brings back the active flags
+        if (rc) return rc;
+    }
+    for (const auto& kv : classes)
+        for (int di : kv.second) c->doms[di].tile = chosen[kv.first];
+    c->tuned = true;
+    rc = restore_state(c, st);
+    if (rc) return rc;
+    if (n_timed) *n_timed = timed;
+    if (cache_path && timed > 0 && !write_cache(cache_path, c->device, cache)) return TPF_EIO;
+    return TPF_OK;
 }
 
 extern "C" int tpf_set_launch_mode(tpf_ctx* c, int32_t mode) {

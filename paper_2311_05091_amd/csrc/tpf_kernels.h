@@ -720,197 +720,6 @@ strip_group_kernel_wide(const DomDev* __restrict__ doms, const int4* __restrict_
     strip_group_body<T, CH, HAS_S, MODE, NW, NT, SHARE>(doms, tiles, ntiles, step_offset, mom_out);
 }
 
-// Same kernel compiled for five wavefronts per SIMD (fewer registers, a few
-// spilled to scratch): more rows in flight per compute unit.
-template <typename T, int CH, bool HAS_S, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
-strip_kernel_o5(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
-                int step_offset, double* __restrict__ mom_out) {
-    strip_body<T, CH, HAS_S, MODE>(doms, tiles, ntiles, step_offset, mom_out);
-}
-
-// ---------------------------------------------------------------------------
-// Pipelined strip kernel: one wavefront per (domain, 60-column strip, CH-row
-// chunk).  Lane l covers column x0 - 2 + l (64 columns); lanes 2..61 update,
-// the two outer lanes on each side only supply the stencil halo, so all lanes
-// run the same instructions.  Each iteration r
-//   1. issues the loads of the next row (CH populations, phi0) and of the NS
-//      populations and lagged fields of the next row to update,
-//   2. sums the CH populations loaded one iteration earlier into phi1 (LDS),
-//   3. computes mubar1 one row above,
-//   4. updates the row two above with operands that are already in registers,
-// so the memory latency of step 1 overlaps a full iteration of arithmetic.
-// ---------------------------------------------------------------------------
-template <typename T, bool HAS_S>
-struct Strip2Shared {
-    T phi0[5][64];
-    T phi1[5][64];
-    T mub[3][64];
-    T psi[HAS_S ? 3 : 1][64];
-};
-
-template <typename T>
-struct RowPre {
-    T g[9];
-    T lAx, lAy, lB, lCxx, lCyy, lCxy;
-};
-
-template <typename T, bool HAS_S>
-__device__ __forceinline__ void strip2_prefetch(const DomDev& d, int r, int x0, int y0, int CH, int lane,
-                                                int cur, bool dS, T (&fP)[9], T& ph0P, RowPre<T>& gP) {
-    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
-    const int N = nx * ny;
-    // CH populations and phi0 of row y0 - 2 + r (issued one iteration ahead)
-    const int yr = y0 - 2 + r;
-    const int sy = map_index(yr, ny, py);
-    const int sx = map_index(x0 - 2 + lane, nx, px);
-    pull9(gpc<T>(d.f[cur]), sx, sy, nx, ny, px, py, N, fP);
-    ph0P = gpc<T>(d.phi0)[sy * nx + sx];
-    // NS populations and lagged fields of the row updated in iteration r
-    const int yu = yr - 2;
-    const int x = x0 - 2 + lane;
-    if (r >= 4 && r < CH + 4 && yu < ny && lane >= 2 && lane < 62 && x < nx) {
-        const int idu = yu * nx + x;
-        pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gP.g);
-        gP.lAx = gpc<T>(d.lagA)[idu];
-        gP.lAy = gpc<T>(d.lagA)[N + idu];
-        gP.lB = gpc<T>(d.lagB)[idu];
-        if (HAS_S && dS) {
-            gP.lCxx = gpc<T>(d.lagC)[idu];
-            gP.lCyy = gpc<T>(d.lagC)[N + idu];
-            gP.lCxy = gpc<T>(d.lagC)[2 * N + idu];
-        }
-    }
-}
-
-template <typename T, bool HAS_S, int MODE>
-__device__ __forceinline__ void strip2_iter(const DomDev& d, const KConst<T>& K, Strip2Shared<T, HAS_S>& sh,
-                                            int r, int x0, int y0, int CH, int lane, int cur, bool dS,
-                                            T (&fS)[9], T (&fP)[9], T (&fU)[9], T& ph0S, T& ph0P,
-                                            RowPre<T>& gU, RowPre<T>& gP, double* __restrict__ mom_out) {
-    const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
-    const int N = nx * ny;
-    const int yr = y0 - 2 + r;
-    // 1. loads for the next iteration
-    if (r + 1 < CH + 4) strip2_prefetch<T, HAS_S>(d, r + 1, x0, y0, CH, lane, cur, dS, fP, ph0P, gP);
-
-    // 2. phi0, phi1 of row yr from the operands loaded in the previous iteration
-    const int slot5 = r % 5;
-    {
-        T s = fS[0];
-#pragma unroll
-        for (int q = 1; q < 9; ++q) s += fS[q];
-        sh.phi1[slot5][lane] = s;
-        sh.phi0[slot5][lane] = ph0S;
-    }
-    __syncthreads();
-
-    // 3. mubar1 (and psi) of row yr - 1 on lanes 1..62
-    const int slot3 = r % 3;
-    if (r >= 2) {
-        if (lane >= 1 && lane < 63) {
-            const int i = lane;
-            const T* pm = sh.phi1[(r + 3) % 5];
-            const T* p0 = sh.phi1[(r + 4) % 5];
-            const T* pp = sh.phi1[slot5];
-            const T* qm = sh.phi0[(r + 3) % 5];
-            const T* q0 = sh.phi0[(r + 4) % 5];
-            const T* qp = sh.phi0[slot5];
-            const T l1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
-                          (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
-            const T l0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
-                          (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
-            T mu0, mu1, mu2;
-            sh.mub[slot3][i] = mubar1<T>(K, q0[i], p0[i], l0, l1, mu0, mu1, mu2);
-        }
-        if constexpr (HAS_S) {
-            if (dS) {
-                const int sx = map_index(x0 - 2 + lane, nx, px);
-                const int sy = map_index(yr - 1, ny, py);
-                sh.psi[slot3][lane] = gpc<T>(d.psi[cur])[sy * nx + sx];
-            }
-        }
-    }
-    __syncthreads();
-
-    // 4. update row yu = yr - 2 on lanes 2..61
-    const int yu = yr - 2;
-    const int x = x0 - 2 + lane;
-    if (r >= 4 && yu < ny && lane >= 2 && lane < 62 && x < nx) {
-        const int i = lane, j = lane;
-        const T* pm = sh.phi1[(r + 2) % 5];
-        const T* p0 = sh.phi1[(r + 3) % 5];
-        const T* pp = sh.phi1[(r + 4) % 5];
-        const T* qm = sh.phi0[(r + 2) % 5];
-        const T* q0 = sh.phi0[(r + 3) % 5];
-        const T* qp = sh.phi0[(r + 4) % 5];
-        const T* mm = sh.mub[(r + 1) % 3];
-        const T* m0 = sh.mub[(r + 2) % 3];
-        const T* mp = sh.mub[slot3];
-        const T gx1 = (T(4) * (p0[i + 1] - p0[i - 1]) + (pp[i + 1] - pp[i - 1] + pm[i + 1] - pm[i - 1])) * T(1.0 / 12.0);
-        const T gy1 = (T(4) * (pp[i] - pm[i]) + (pp[i + 1] - pm[i + 1] + pp[i - 1] - pm[i - 1])) * T(1.0 / 12.0);
-        const T lap1 = (T(4) * (p0[i + 1] + p0[i - 1] + pp[i] + pm[i]) +
-                        (pp[i + 1] + pp[i - 1] + pm[i + 1] + pm[i - 1]) - T(20) * p0[i]) * T(1.0 / 6.0);
-        const T gx0 = (T(4) * (q0[i + 1] - q0[i - 1]) + (qp[i + 1] - qp[i - 1] + qm[i + 1] - qm[i - 1])) * T(1.0 / 12.0);
-        const T gy0 = (T(4) * (qp[i] - qm[i]) + (qp[i + 1] - qm[i + 1] + qp[i - 1] - qm[i - 1])) * T(1.0 / 12.0);
-        const T lap0 = (T(4) * (q0[i + 1] + q0[i - 1] + qp[i] + qm[i]) +
-                        (qp[i + 1] + qp[i - 1] + qm[i + 1] + qm[i - 1]) - T(20) * q0[i]) * T(1.0 / 6.0);
-        const T gmx = (T(4) * (m0[j + 1] - m0[j - 1]) + (mp[j + 1] - mp[j - 1] + mm[j + 1] - mm[j - 1])) * T(1.0 / 12.0);
-        const T gmy = (T(4) * (mp[j] - mm[j]) + (mp[j + 1] - mm[j + 1] + mp[j - 1] - mm[j - 1])) * T(1.0 / 12.0);
-        T dpx = T(0), dpy = T(0);
-        if constexpr (HAS_S) {
-            if (dS) {
-                const T* sm = sh.psi[(r + 1) % 3];
-                const T* s0 = sh.psi[(r + 2) % 3];
-                const T* sp = sh.psi[slot3];
-                dpx = (T(4) * (s0[j + 1] - s0[j - 1]) + (sp[j + 1] - sp[j - 1] + sm[j + 1] - sm[j - 1])) * T(1.0 / 12.0);
-                dpy = (T(4) * (sp[j] - sm[j]) + (sp[j + 1] - sm[j + 1] + sp[j - 1] - sm[j - 1])) * T(1.0 / 12.0);
-            }
-        }
-        node_update<T, MODE>(d, K, dS, (int64_t)yu * nx, (uint32_t)x * (uint32_t)sizeof(T), N, x, yu, q0[i], p0[i], gx0, gy0, lap0, gx1, gy1, lap1, m0[j],
-                             gmx, gmy, dpx, dpy, fU, gU.g, gU.lAx, gU.lAy, gU.lB, gU.lCxx, gU.lCyy, gU.lCxy,
-                             cur, mom_out);
-    }
-}
-
-template <typename T, int CH, bool HAS_S, int MODE>
-__global__ void __launch_bounds__(64)
-strip2_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles,
-              int step_offset, double* __restrict__ mom_out) {
-    __shared__ Strip2Shared<T, HAS_S> sh;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    if (t >= ntiles) return;
-    const int4 tile = tiles[t];
-    const DomDev& d = doms[tile.x];
-    if (!d.live && MODE == kModeStep) return;
-    const KConst<T> K = kconst<T>(d);
-    const int cur = (d.parity + step_offset) & 1;
-    const bool dS = HAS_S && d.has_s;
-    const int lane = threadIdx.x;
-    const int x0 = tile.y, y0 = tile.z;
-    T F0[9], F1[9], F2[9], F3[9];
-    T P0 = T(0), P1 = T(0);
-    RowPre<T> G0, G1;
-    G0.lCxx = G0.lCyy = G0.lCxy = G1.lCxx = G1.lCyy = G1.lCxy = T(0);
-    // prologue: operands of iteration 0
-    strip2_prefetch<T, HAS_S>(d, 0, x0, y0, CH, lane, cur, dS, F0, P0, G0);
-    // iteration r sums F[r % 4], prefetches into F[(r + 1) % 4], updates with
-    // F[(r + 2) % 4] (loaded for row r - 2); G and P alternate
-    constexpr int R = CH + 4;
-    for (int r = 0; r < R; r += 4) {
-        strip2_iter<T, HAS_S, MODE>(d, K, sh, r, x0, y0, CH, lane, cur, dS, F0, F1, F2, P0, P1, G0, G1, mom_out);
-        if (r + 1 < R)
-            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 1, x0, y0, CH, lane, cur, dS, F1, F2, F3, P1, P0, G1, G0,
-                                        mom_out);
-        if (r + 2 < R)
-            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 2, x0, y0, CH, lane, cur, dS, F2, F3, F0, P0, P1, G0, G1,
-                                        mom_out);
-        if (r + 3 < R)
-            strip2_iter<T, HAS_S, MODE>(d, K, sh, r + 3, x0, y0, CH, lane, cur, dS, F3, F0, F1, P1, P0, G1, G0,
-                                        mom_out);
-    }
-}
-
 // Initial state (per node): f = f^eq(phi1, eta mubar1, u = 0), g = g^eq(P = 0,
 // u = 0) = gauge delta_q0, lagged fields zero.  phi1 comes from a float64 field.
 template <typename T>

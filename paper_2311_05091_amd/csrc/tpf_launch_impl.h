@@ -36,20 +36,6 @@ hipError_t launch_strip_group_wide_t(const TileLaunch& a) {
     return hipGetLastError();
 }
 
-template <typename T, int CH, bool S, int MODE>
-hipError_t launch_strip_o5_t(const TileLaunch& a) {
-    hipLaunchKernelGGL((strip_kernel_o5<T, CH, S, MODE>), dim3(a.ntiles), dim3(64), 0, a.stream, a.doms,
-                       a.tiles, a.ntiles, a.offset, a.mom);
-    return hipGetLastError();
-}
-
-template <typename T, int CH, bool S, int MODE>
-hipError_t launch_strip2_t(const TileLaunch& a) {
-    hipLaunchKernelGGL((strip2_kernel<T, CH, S, MODE>), dim3(a.ntiles), dim3(64), 0, a.stream, a.doms, a.tiles,
-                       a.ntiles, a.offset, a.mom);
-    return hipGetLastError();
-}
-
 template <typename T, bool S, int MODE>
 hipError_t launch_shape(int code, const TileLaunch& a) {
     switch (code) {
@@ -60,22 +46,11 @@ hipError_t launch_shape(int code, const TileLaunch& a) {
         case 22: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 0, true>(a);
         case 23: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 3, false>(a);
         case 24: return launch_strip_group_wide_t<T, 64, S, MODE, 4, 1, true>(a);
-        case 15: return launch_strip_o5_t<T, 32, S, MODE>(a);
-        case 16: return launch_strip_o5_t<T, 16, S, MODE>(a);
-        case 12: return launch_strip2_t<T, 16, S, MODE>(a);
-        case 13: return launch_strip2_t<T, 32, S, MODE>(a);
-        case 14: return launch_strip2_t<T, 64, S, MODE>(a);
         case 8: return launch_strip_t<T, 16, S, MODE>(a);
         case 9: return launch_strip_t<T, 32, S, MODE>(a);
         case 10: return launch_strip_t<T, 64, S, MODE>(a);
-        case 11: return launch_strip_t<T, 128, S, MODE>(a);
         case 1: return launch_step_t<T, 64, 4, S, MODE>(a);
         case 2: return launch_step_t<T, 64, 8, S, MODE>(a);
-        case 3: return launch_step_t<T, 64, 16, S, MODE>(a);
-        case 4: return launch_step_t<T, 128, 8, S, MODE>(a);
-        case 5: return launch_step_t<T, 32, 8, S, MODE>(a);
-        case 6: return launch_step_t<T, 64, 32, S, MODE>(a);
-        case 7: return launch_step_t<T, 128, 16, S, MODE>(a);
     }
     return hipErrorInvalidValue;
 }

@@ -94,6 +94,9 @@ def library() -> C.CDLL:
         "tpf_get_tile": (C.c_int, [V, _I32, _I32, _I32]),
         "tpf_tile_codes": (C.c_int, [_I32, _I32, _I32, _I32]),
         "tpf_autotune": (C.c_int, [V, C.c_int32, _D]),
+        "tpf_size_class": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.c_int32]),
+        "tpf_autotune_classes": (C.c_int, [V, C.c_int32, C.c_char_p, _I32]),
+        "tpf_domain_tile": (C.c_int, [V, C.c_int32, _I32]),
         "tpf_set_launch_mode": (C.c_int, [V, C.c_int32]),
         "tpf_bytes_per_node": (C.c_int, [V, C.c_int32, _D]),
         "tpf_num_domains": (C.c_int, [V, _I32]),
@@ -115,7 +118,8 @@ def library() -> C.CDLL:
 EXPORTED = ("tpf_default_params", "tpf_create", "tpf_add_domain", "tpf_arena_bytes", "tpf_finalize",
             "tpf_step", "tpf_run_to_residual", "tpf_read_moments", "tpf_read_diag", "tpf_set_phi1", "tpf_set_active",
             "tpf_get_populations", "tpf_save", "tpf_load", "tpf_set_tile", "tpf_get_tile",
-            "tpf_tile_codes", "tpf_autotune", "tpf_set_launch_mode", "tpf_bytes_per_node",
+            "tpf_tile_codes", "tpf_autotune", "tpf_size_class", "tpf_autotune_classes", "tpf_domain_tile",
+            "tpf_set_launch_mode", "tpf_bytes_per_node",
             "tpf_num_domains", "tpf_domain_size", "tpf_derived", "tpf_kernel_timing",
             "tpf_copy_bandwidth", "tpf_strerror", "tpf_destroy")
 
@@ -170,6 +174,13 @@ def params_from_spec(spec: DomainSpec) -> DomainParams:
     p.wall_center[:] = list(spec.wall_center)
     p.rho_gauge = spec.rho_gauge
     return p
+
+
+def size_class(precision: int, nx: int, ny: int, has_s: bool) -> str:
+    """The autotuner's size class of a domain (host only)."""
+    buf = C.create_string_buffer(64)
+    _check(library().tpf_size_class(precision, nx, ny, 1 if has_s else 0, buf, 64), "tpf_size_class")
+    return buf.value.decode()
 
 
 def tile_codes():
@@ -296,6 +307,19 @@ class Context:
         ms = C.c_double()
         _check(self.lib.tpf_autotune(self._h, int(steps), C.byref(ms)), "tpf_autotune")
         return ms.value
+
+    def autotune_classes(self, steps: int = 20, cache_path: Optional[str] = None) -> int:
+        """Per-size-class tile choice (timed, or read from the JSON cache);
+        returns the number of classes that were timed."""
+        n = C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self.lib.tpf_autotune_classes(self._h, int(steps), path, C.byref(n)), "tpf_autotune_classes")
+        return n.value
+
+    def domain_tile(self, did: int) -> int:
+        c = C.c_int32()
+        _check(self.lib.tpf_domain_tile(self._h, int(did), C.byref(c)), "tpf_domain_tile")
+        return c.value
 
     def bytes_per_node(self, did: int = 0) -> float:
         b = C.c_double()

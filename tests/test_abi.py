@@ -41,6 +41,24 @@ def test_strerror_and_tile_table_without_device():
     assert lib.tpf_tile_codes(ctypes.byref(n), None, None, None) == 0 and n.value >= 4
 
 
+def test_size_class_names_without_device():
+    """The autotuner's size classes: precision, S flag, and nx, ny rounded up
+    to powers of two; bad arguments and short buffers are rejected."""
+    lib = _lib("libtpf.so")
+    f = lib.tpf_size_class
+    f.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_char_p, ctypes.c_int32]
+    buf = ctypes.create_string_buffer(64)
+    for args, want in (((32, 256, 256, 0), "p32_s0_w256_h256"), ((32, 257, 129, 0), "p32_s0_w512_h256"),
+                       ((64, 128, 512, 1), "p64_s1_w128_h512"), ((32, 4096, 2048, 0), "p32_s0_w4096_h2048"),
+                       ((32, 3, 3, 0), "p32_s0_w4_h4")):
+        assert f(*args, buf, 64) == 0 and buf.value.decode() == want, args
+    EINVAL = -1
+    assert f(16, 64, 64, 0, buf, 64) == EINVAL
+    assert f(32, 0, 64, 0, buf, 64) == EINVAL
+    assert f(32, 64, 64, 0, buf, 8) == EINVAL
+    assert f(32, 64, 64, 0, None, 64) == EINVAL
+
+
 def test_default_params_are_stable_reading():
     from paper_2311_05091_amd import lbm
     lib = lbm.library()

@@ -125,18 +125,17 @@ def test_fp64_parity(orc, name, factory, steps):
 def test_every_tile_shape_consistent(orc):
     """The tile shape changes only the work decomposition: shapes served by the
     same kernel source agree bit for bit (the strip kernel alone or in
-    lockstep groups, codes 8-11 and 17-24); the tile (codes 1-7), strip,
-    pipelined strip (12-14) and five-waves strip (15-16) kernels may contract
-    multiply-adds differently, so across them the results agree to rounding
-    (FP32: 2e-6 of the largest population after 40 steps; FP64: 1e-13)."""
+    lockstep groups, codes 8-10 and 17-24); the tile kernel (codes 1, 2) and
+    the strip kernels may contract multiply-adds differently, so across them
+    the results agree to rounding (FP32: 2e-6 of the largest population after
+    40 steps; FP64: 1e-13)."""
     from paper_2311_05091_amd.lbm import tile_codes
     sp = G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0, rho=(1.0, 1.0, 0.1),
                           mu=(0.15, 0.15, 0.015))
     ref = {}
     for code, tx, ty in tile_codes():
         _say("tile", code, tx, ty)
-        fam = ("tile" if code < 8 else "strip" if code < 12 or code >= 17 else "strip2" if code < 15
-               else "strip_o5")
+        fam = "tile" if code < 8 else "strip"
         for prec in (32, 64):
             ctx = gpu_context([sp], precision=prec, tile=code)
             ctx.step(40)
@@ -147,7 +146,7 @@ def test_every_tile_shape_consistent(orc):
                 ref[key] = (f, g)
             else:
                 assert np.array_equal(f, ref[key][0]) and np.array_equal(g, ref[key][1]), (code, prec)
-            for other_fam in ("tile", "strip", "strip2", "strip_o5"):
+            for other_fam in ("tile", "strip"):
                 other = (other_fam, prec)
                 if other_fam == fam or other not in ref:
                     continue

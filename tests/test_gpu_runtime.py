@@ -193,6 +193,55 @@ def test_autotune_restores_state_and_picks_known_tile():
     ctx.close()
 
 
+def test_class_autotune_cache_is_reused_and_state_restored(tmp_path):
+    """Per-size-class autotuning: three classes (128^2 without S, 300 x 200
+    without S, 128^2 with S) are timed, each domain gets its class's code, the
+    state is restored, and the JSON cache written for this device makes a
+    second context take the same codes without timing and step to the same
+    bits.  A cache of another device is ignored and replaced."""
+    ratio10 = dict(rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015))
+    specs = [G.solid_disk_box(n=128, Rs=12, R0=15), G.solid_disk_box(n=128, Rs=10, R0=17),
+             G.solid_disk_box(n=300, ny=200, Rs=20, R0=25, periodic_y=0),
+             G.solid_disk_box(n=300, ny=200, Rs=24, R0=20, periodic_y=0),
+             G.solid_disk_box(n=128, Rs=12, R0=15, **ratio10)]
+    cache = str(tmp_path / "tiles.json")
+    with open(cache, "w") as f:
+        f.write('{\n  "format": "tpf-autotune-1",\n  "device": "other:1",\n  "entries": {\n'
+                '    "p32_s0_w128_h128": {"code": 1, "ms_per_step": 0.001}\n  }\n}\n')
+    _say("class autotune")
+    runs = []
+    for attempt in range(2):
+        ctx = gpu_context(specs, precision=32)
+        ctx.step(10)
+        before = [ctx.populations(i) for i in range(len(specs))]
+        n_timed = ctx.autotune_classes(steps=3, cache_path=cache)
+        assert n_timed == (3 if attempt == 0 else 0)
+        for i in range(len(specs)):
+            f, g = ctx.populations(i)
+            assert np.array_equal(f, before[i][0]) and np.array_equal(g, before[i][1]), (attempt, i)
+            assert ctx.diag(i)["steps"] == 10
+        codes = [ctx.domain_tile(i) for i in range(len(specs))]
+        assert codes[0] == codes[1] and codes[2] == codes[3]
+        ctx.step(20)
+        runs.append((codes, [ctx.populations(i) for i in range(len(specs))]))
+        ctx.close()
+    text = open(cache).read()
+    assert '"device": "other:1"' not in text and text.count('"code"') == 3
+    for key in ("p32_s0_w128_h128", "p32_s0_w512_h256", "p32_s1_w128_h128"):
+        assert key in text
+    assert runs[0][0] == runs[1][0]
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # mixed codes in one step agree with one code for all to FP32 rounding
+    one = gpu_context(specs, precision=32, tile=9)
+    one.step(30)
+    for i, (f, g) in enumerate(runs[0][1]):
+        f1, g1 = one.populations(i)
+        assert np.abs(f - f1).max() <= 2e-6 * np.abs(f1).max(), i
+        assert np.abs(g - g1).max() <= 2e-6 * max(np.abs(g1).max(), 1e-3), i
+    one.close()
+
+
 EDGE = [
     ("min_3x3_periodic", lambda: G.DomainSpec(nx=3, ny=3, phi0=np.zeros((3, 3)),
                                               phi1=np.array([[0.1, 0.5, 0.9]] * 3), periodic_y=1)),
