@@ -80,7 +80,9 @@ void tpf_default_params(tpf_domain_params* p, int32_t nx, int32_t ny);
 
 /* Creates a context.  precision: 32 (FP32 storage and arithmetic, FP64
  * reductions) or 64 (FP64 throughout).  hip_stream: a hipStream_t or NULL.
- * Fails with TPF_EDEVICE when no device is present. */
+ * Touches no device: domains can be added and the arena size, derived
+ * constants and bytes per node queried on a host without a GPU;
+ * tpf_finalize fails with TPF_EDEVICE when no device is present. */
 int tpf_create(tpf_ctx** out, int32_t precision, void* hip_stream);
 
 /* Adds a domain: phi0 (solid field, fixed) and phi1_init, each nx*ny
@@ -96,7 +98,8 @@ int tpf_arena_bytes(tpf_ctx* ctx, uint64_t* bytes);
 /* Allocates (or binds) the device arena, derives the per-domain constants
  * (spreading factor, gamma_p, eta, Sec. 2.2-3) and initialises every domain:
  * f = f^eq(phi1, mubar1, u = 0), g = g^eq(P = 0, u = 0), lagged fields 0.
- * arena: device pointer of >= tpf_arena_bytes() bytes, 256-byte aligned, or NULL. */
+ * arena: device pointer of >= tpf_arena_bytes() bytes, 256-byte aligned, or NULL.
+ * TPF_EDEVICE when no device is present. */
 int tpf_finalize(tpf_ctx* ctx, void* arena, uint64_t arena_bytes);
 
 /* Advances every live domain by nsteps coupled time steps (Sec. 3): per step

@@ -50,7 +50,8 @@ typedef struct tpf3_ctx tpf3_ctx;
 
 void tpf3_default_params(tpf3_domain_params* p, int32_t nx, int32_t ny, int32_t nz);
 
-/* precision 32 (FP32 storage and arithmetic, FP64 mass sums) or 64. */
+/* precision 32 (FP32 storage and arithmetic, FP64 mass sums) or 64.  Touches
+ * no device (tpf3_finalize returns TPF_EDEVICE when there is none). */
 int tpf3_create(tpf3_ctx** out, int32_t precision, void* hip_stream);
 
 /* phi0, phi1_init: nx*ny*nz float64 each.  TPF_EINVAL for sizes < 3 or more

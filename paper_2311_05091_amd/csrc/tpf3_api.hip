@@ -271,9 +271,7 @@ static hipError_t launch_split(tpf3_ctx* c, int mode, int ntiles, int n_noS, int
 
 extern "C" int tpf3_create(tpf3_ctx** out, int32_t precision, void* hip_stream) {
     if (!out || (precision != 32 && precision != 64)) return TPF_EINVAL;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TPF_EDEVICE;
-    tpf3_ctx* c = new tpf3_ctx();
+    tpf3_ctx* c = new tpf3_ctx();  // no device work before tpf3_finalize
     c->precision = precision;
     c->stream = (hipStream_t)hip_stream;
     *out = c;
@@ -305,6 +303,8 @@ extern "C" int tpf3_arena_bytes(tpf3_ctx* c, uint64_t* bytes) {
 extern "C" int tpf3_finalize(tpf3_ctx* c, void* arena, uint64_t arena_bytes) {
     if (!c) return TPF_EINVAL;
     if (c->finalized || c->doms.empty()) return TPF_ESTATE;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TPF_EDEVICE;
     const size_t need = total_bytes3(c);
     if (arena) {
         if (arena_bytes < need || ((uintptr_t)arena & 255)) return TPF_EINVAL;

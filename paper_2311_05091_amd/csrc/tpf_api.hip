@@ -567,13 +567,7 @@ static int reduce(tpf_ctx* c, const std::vector<int>& which, bool update_snap) {
 // ---------------------------------------------------------------------------
 extern "C" int tpf_create(tpf_ctx** out, int32_t precision, void* hip_stream) {
     if (!out || (precision != 32 && precision != 64)) return TPF_EINVAL;
-    int ndev = 0;
-    const hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess || ndev <= 0) {
-        std::fprintf(stderr, "tpf: no usable device (%s, %d devices)\n", hipGetErrorString(e), ndev);
-        return TPF_EDEVICE;
-    }
-    tpf_ctx* c = new tpf_ctx();
+    tpf_ctx* c = new tpf_ctx();  // no device work before tpf_finalize
     c->precision = precision;
     c->stream = (hipStream_t)hip_stream;
     *out = c;
@@ -636,6 +630,14 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
     if (!c) return TPF_EINVAL;
     if (c->finalized) return TPF_ESTATE;
     if (c->doms.empty()) return TPF_ESTATE;
+    {
+        int ndev = 0;
+        const hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess || ndev <= 0) {
+            std::fprintf(stderr, "tpf: no usable device (%s, %d devices)\n", hipGetErrorString(e), ndev);
+            return TPF_EDEVICE;
+        }
+    }
     const uint64_t need = total_bytes(c);
     if (arena) {
         if (arena_bytes < need || ((uintptr_t)arena & 255)) return TPF_EINVAL;
