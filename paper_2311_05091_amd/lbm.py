@@ -228,11 +228,16 @@ class Context:
         self.specs.append(spec)
         return did.value
 
-    def finalize(self):
+    def finalize(self, fill: Optional[int] = None):
+        """Binds the arena and initialises the domains.  fill: byte value the
+        arena is set to first (tests use it to show that no step reads memory
+        that initialisation did not write)."""
         nbytes = C.c_uint64()
         _check(self.lib.tpf_arena_bytes(self._h, C.byref(nbytes)), "tpf_arena_bytes")
         if self.use_torch_arena:
             self._arena = self._torch.empty(int(nbytes.value), dtype=self._torch.uint8, device=self.device)
+            if fill is not None:
+                self._arena.fill_(int(fill))
             ptr = C.c_void_p(self._arena.data_ptr())
         else:
             ptr = C.c_void_p(None)
