@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpf_oracle.c")
 _SRC3 = os.path.join(_HERE, "tpf_oracle3d.c")
+_SRC3F = os.path.join(_HERE, "tpf_oracle3f.c")
 _LIB_PATH = os.path.join(_HERE, "libtpf_oracle.so")
 _lib = None
 
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, _SRC3, "-lm"])
+                               "-o", tmp, _SRC, _SRC3, _SRC3F, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -57,6 +58,20 @@ class Derived(C.Structure):
         ("k", C.c_double), ("sigma01", C.c_double), ("sigma02", C.c_double),
         ("gamma", C.c_double * 3), ("gammaT", C.c_double), ("eta", C.c_double),
         ("cs2", C.c_double), ("w", C.c_double * 9), ("Kp", C.c_double),
+    ]
+
+
+class Params3F(C.Structure):
+    """Parameters of a 3f-model domain, field for field ``orc3f_params``."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+        ("d0", C.c_double), ("D", C.c_double),
+        ("sigma01", C.c_double), ("sigma02", C.c_double), ("sigma12", C.c_double),
+        ("rho", C.c_double * 3), ("mu", C.c_double * 3),
+        ("M_cst", C.c_double), ("M_deg", C.c_double), ("tau_phi", C.c_double),
+        ("s_phi", C.c_double * 4), ("s_g", C.c_double * 4),
+        ("Fb", C.c_double * 2), ("rho_gauge", C.c_double),
     ]
 
 
@@ -122,6 +137,18 @@ def _lib_handle():
         lib.orc_visc_rate.restype = C.c_double
         lib.orc_visc_rate.argtypes = [C.c_double] * 4
         lib.orc_num_threads.restype = C.c_int
+        if hasattr(lib, "orc3f_create"):
+            lib.orc3f_create.restype = C.c_void_p
+            lib.orc3f_create.argtypes = [C.POINTER(Params3F), _D, _D]
+            lib.orc3f_free.argtypes = [C.c_void_p]
+            lib.orc3f_step.argtypes = [C.c_void_p, C.c_int64]
+            lib.orc3f_moments.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
+            lib.orc3f_mass.argtypes = [C.c_void_p, _D]
+            lib.orc3f_get_state.argtypes = [C.c_void_p, _D, _D, _D, _D]
+            lib.orc3f_step_count.restype = C.c_int64
+            lib.orc3f_step_count.argtypes = [C.c_void_p]
+            lib.orc3f_derive.restype = C.c_int
+            lib.orc3f_derive.argtypes = [C.POINTER(Params3F), _D, _D, _D]
         if hasattr(lib, "orc3_create"):
             lib.orc3_create.restype = C.c_void_p
             lib.orc3_create.argtypes = [C.POINTER(Params3), _D, _D]
@@ -523,3 +550,75 @@ class Sim3:
         g = np.zeros(3)
         _lib_handle().orc3_derived(self._h, C.byref(k), _ptr(g), C.byref(eta))
         return {"k": k.value, "gamma": list(g), "eta": eta.value}
+
+
+def make_params3f(nx, ny, *, periodic_x=1, periodic_y=0, d0=0.5, D=4.0, sigma01=0.01, sigma02=0.01,
+                  sigma12=0.01, rho=(1.0, 1.0, 1.0), mu=(0.15, 0.15, 0.15), M_cst=0.0, M_deg=0.01, tau_phi=0.8,
+                  s_phi=(1.0, 1.0, 1.0, 1.0), s_g=(1.0, 1.0, 1.0, 1.0), Fb=(0.0, 0.0), rho_gauge=0.0) -> Params3F:
+    """Parameters of the 3f model (three fluids, phi0 evolving)."""
+    p = Params3F()
+    p.nx, p.ny, p.periodic_x, p.periodic_y = nx, ny, periodic_x, periodic_y
+    p.d0, p.D = d0, D
+    p.sigma01, p.sigma02, p.sigma12 = sigma01, sigma02, sigma12
+    p.rho[:] = list(rho)
+    p.mu[:] = list(mu)
+    p.M_cst, p.M_deg, p.tau_phi = M_cst, M_deg, tau_phi
+    p.s_phi[:] = list(s_phi)
+    p.s_g[:] = list(s_g)
+    p.Fb[:] = list(Fb)
+    p.rho_gauge = rho_gauge
+    return p
+
+
+def derive3f(p: Params3F):
+    """(gamma[3], gammaT, eta[2]) of the 3f model, or None if a gamma_p <= 0."""
+    g, gT, eta = np.zeros(3), C.c_double(), np.zeros(2)
+    rc = _lib_handle().orc3f_derive(C.byref(p), _ptr(g), C.byref(gT), _ptr(eta))
+    return None if rc else (g, gT.value, eta)
+
+
+class Sim3F:
+    """One 2D domain of the 3f model advanced by the oracle; arrays [ny, nx]."""
+
+    NLAG = 9  # phi0 u, phi1 u, (rho u - S).u, sym(S u) (xx, yy, xy), psi
+
+    def __init__(self, params: Params3F, phi0, phi1):
+        self.params = params
+        self.shape = (params.ny, params.nx)
+        n = params.nx * params.ny
+        self._phi0 = _arr(phi0, n)
+        self._phi1 = _arr(phi1, n)
+        self._h = _lib_handle().orc3f_create(C.byref(params), _ptr(self._phi0), _ptr(self._phi1))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib_handle().orc3f_free(h)
+            self._h = None
+
+    def step(self, nsteps: int = 1):
+        _lib_handle().orc3f_step(self._h, int(nsteps))
+
+    @property
+    def steps(self) -> int:
+        return _lib_handle().orc3f_step_count(self._h)
+
+    def moments(self):
+        out = [np.zeros(self.shape) for _ in range(5)]
+        _lib_handle().orc3f_moments(self._h, *[_ptr(a) for a in out])
+        return tuple(out)  # phi0, phi1, ux, uy, p
+
+    def mass(self):
+        m = np.zeros(2)
+        _lib_handle().orc3f_mass(self._h, _ptr(m))
+        return m
+
+    def get_state(self):
+        f0 = np.zeros((9,) + self.shape)
+        f1 = np.zeros((9,) + self.shape)
+        g = np.zeros((9,) + self.shape)
+        lag = np.zeros((self.NLAG,) + self.shape)
+        _lib_handle().orc3f_get_state(self._h, _ptr(f0), _ptr(f1), _ptr(g), _ptr(lag))
+        return f0, f1, g, lag

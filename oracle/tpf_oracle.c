@@ -198,7 +198,7 @@ void orc_relaxation_matrix(double cs2, const double Kdiag[9], double S[81])
 
 /* MRT collision in natural-moment space (Sec. 4) with given M0, M0^-1, S:
  *   m = M0 f,  m* = m - S (m - m_eq) + (I - S/2) M0 R,  f* = M0^-1 m*. */
-static void collide_with(const double M0[81], const double M0inv[81], const double S[81],
+void orc_collide_with(const double M0[81], const double M0inv[81], const double S[81],
                          const double f[9], const double feq[9], const double R[9], double fout[9])
 {
     double m[9], meq[9], mR[9], d[9], Sd[9], SR[9], ms[9];
@@ -220,7 +220,7 @@ void orc_collide(double cs2, const double Kdiag[9], const double f[9],
     orc_M0(M0);
     orc_inverse9(M0, M0inv);
     orc_relaxation_matrix(cs2, Kdiag, S);
-    collide_with(M0, M0inv, S, f, feq, R, fout);
+    orc_collide_with(M0, M0inv, S, f, feq, R, fout);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -556,7 +556,7 @@ static void macro_and_collide(orc_sim* s, int collide)
             for (int i = 0; i < 9; ++i) fl[i] = s->f[(size_t)i * n + id];
             orc_feq(P->d0, phi1, d->eta * mub, Anx, Any, feq);
             orc_Rpop(P->d0, Anx - Ax[id], Any - Ay[id], a, d->eta * gmx, d->eta * gmy, R);
-            collide_with(s->M0, s->M0inv, s->Sphi, fl, feq, R, fo);
+            orc_collide_with(s->M0, s->M0inv, s->Sphi, fl, feq, R, fo);
             for (int i = 0; i < 9; ++i) s->fpost[(size_t)i * n + id] = fo[i];
 
             /* ---- NS collision ---- */
@@ -575,7 +575,7 @@ static void macro_and_collide(orc_sim* s, int collide)
             for (int r = 0; r < 9; ++r)
                 for (int c = 0; c < 9; ++c) KN[r * 9 + c] = Kg[r] * s->N[r * 9 + c];
             matmul9(s->Ninv, KN, Sg);            /* S = N^-1 K N */
-            collide_with(s->M0, s->M0inv, Sg, gl, geq, Fp, go);
+            orc_collide_with(s->M0, s->M0inv, Sg, gl, geq, Fp, go);
             for (int i = 0; i < 9; ++i) s->gpost[(size_t)i * n + id] = go[i];
 
             lag_new[0 * n + id] = Anx;

@@ -242,6 +242,35 @@ def test_class_autotune_cache_is_reused_and_state_restored(tmp_path):
     one.close()
 
 
+def test_step_reads_no_memory_initialisation_left_unwritten():
+    """The same batch (walls, periodic, the S flux, ragged sizes, a moving
+    solid) in arenas filled with zeros and with NaN bytes before
+    tpf_finalize, stepped in every launch mode: bitwise equal states, so no
+    kernel reads arena memory that initialisation did not write."""
+    from paper_2311_05091_amd.lbm import Context
+    ratio10 = dict(rho=(1.0, 1.0, 0.1), mu=(0.15, 0.15, 0.015))
+    specs = [G.solid_disk_box(n=67, ny=23, Rs=5.0, R0=6.0, periodic_y=0),
+             G.solid_disk_box(n=131, ny=37, Rs=7.0, R0=9.0, periodic_y=0, **ratio10),
+             G.with_params(G.solid_disk_box(n=40, ny=33, **ratio10), u_wall=(1e-3, 0.0), omega_wall=1e-4,
+                           wall_center=(12.0, 13.2))]
+    _say("arena fill")
+    for mode in (0, 1, 2):
+        out = []
+        for fill in (0x00, 0xFF):
+            ctx = Context(precision=32)
+            for sp in specs:
+                ctx.add_domain(sp)
+            ctx.finalize(fill=fill)
+            ctx.set_launch_mode(mode)
+            ctx.step(60)
+            ctx.run_to_residual(1e-30, check_every=20, max_steps=40)
+            out.append([ctx.populations(i) for i in range(len(specs))])
+            ctx.close()
+        for i, (a, b) in enumerate(zip(*out)):
+            assert np.isfinite(a[0]).all() and np.isfinite(a[1]).all(), (mode, i)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (mode, i)
+
+
 EDGE = [
     ("min_3x3_periodic", lambda: G.DomainSpec(nx=3, ny=3, phi0=np.zeros((3, 3)),
                                               phi1=np.array([[0.1, 0.5, 0.9]] * 3), periodic_y=1)),

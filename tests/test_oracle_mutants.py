@@ -17,6 +17,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tpf_oracle.c")
 SRC3 = os.path.join(ROOT, "oracle", "tpf_oracle3d.c")
+SRC3F = os.path.join(ROOT, "oracle", "tpf_oracle3f.c")
 NORMAL = "tests/test_oracle_consistency.py::test_translating_interface_density_ratio_10"
 TANGENT = "tests/test_oracle_consistency.py::test_tangential_flow_along_relaxing_interface"
 CHANNEL = "tests/test_oracle_solid.py::test_diffuse_channel_momentum_balance"
@@ -25,6 +26,9 @@ SPIN = "tests/test_oracle_solid.py::test_spinning_cavity_rigid_rotation"
 NORMAL3 = "tests/test_oracle3d.py::test_translating_interface_3d_density_ratio_10"
 TANGENT3 = "tests/test_oracle3d.py::test_tangential_flow_along_relaxing_interface_3d"
 LAPLACE3 = "tests/test_oracle3d.py::test_laplace_law_sphere"
+RELABEL3F = "tests/test_oracle_3f.py::test_3f_exchanging_phases_0_and_1"
+LAPLACE3F = "tests/test_oracle_3f.py::test_3f_laplace_law_for_phase_0_in_phase_2"
+LENS3F = "tests/test_oracle_3f.py::test_3f_lens_corner_angles_follow_neumann_triangle"
 
 # name, original text (must occur exactly once), replacement, pin that must fail
 MUTANTS = [
@@ -69,14 +73,16 @@ MUTANTS3 = [
 ]
 
 
-def _run_pin(tmp_path, name, src_text, pin, src3_text=None):
+def _run_pin(tmp_path, name, src_text, pin, src3_text=None, src3f_text=None):
     c = tmp_path / (name + ".c")
     c3 = tmp_path / (name + "_3d.c")
+    c3f = tmp_path / (name + "_3f.c")
     so = tmp_path / (name + ".so")
     c.write_text(src_text)
     c3.write_text(src3_text if src3_text is not None else open(SRC3).read())
+    c3f.write_text(src3f_text if src3f_text is not None else open(SRC3F).read())
     subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c),
-                           str(c3), "-lm"])
+                           str(c3), str(c3f), "-lm"])
     env = dict(os.environ, TPF_ORACLE_LIB=str(so))
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
@@ -100,4 +106,29 @@ def test_mutant_3d_fails_its_pin(tmp_path, name, orig, repl, pin):
     src3 = open(SRC3).read()
     assert src3.count(orig) == 1, "mutation site changed: " + orig
     r = _run_pin(tmp_path, name, open(SRC).read(), pin, src3.replace(orig, repl))
+    assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
+
+
+# mistakes planted in the 3f-model oracle
+MUTANTS3F = [
+    ("3f_S_phase1_only", "Mob * ((r0 - r2) * gm0x / s->gamma[0] + (r1 - r2) * gm1x / s->gamma[1])",
+     "Mob * ((r1 - r2) * gm1x / s->gamma[1])", RELABEL3F),
+    ("3f_mobility_of_2f1s", "double fdeg = (1.0 - phi0) * (1.0 - phi1) * (1.0 - phi2);",
+     "double fdeg = phi1 * (1.0 - phi1) * (1.0 - phi0);", RELABEL3F),
+    ("3f_eta_of_phase1", "eta[p] = (P->M_cst + P->M_deg) / (gamma[p] *", "eta[p] = (P->M_cst + P->M_deg) / (gamma[1] *",
+     RELABEL3F),
+    ("3f_viscosity_with_solid_factor", "double s2a = orc_visc_rate(mu_v, rho, 0.0,", "double s2a = orc_visc_rate(mu_v, rho, phi0,",
+     RELABEL3F),
+    ("3f_gamma2_tensions_swapped", "gamma[2] = P->sigma02 + P->sigma12 - P->sigma01;",
+     "gamma[2] = P->sigma01 + P->sigma12 - P->sigma02;", LAPLACE3F),
+    ("3f_gamma0_tensions_swapped", "gamma[0] = P->sigma01 + P->sigma02 - P->sigma12;",
+     "gamma[0] = P->sigma01 + P->sigma12 - P->sigma02;", LENS3F),
+]
+
+
+@pytest.mark.parametrize("name,orig,repl,pin", MUTANTS3F, ids=[m[0] for m in MUTANTS3F])
+def test_mutant_3f_fails_its_pin(tmp_path, name, orig, repl, pin):
+    src3f = open(SRC3F).read()
+    assert src3f.count(orig) == 1, "mutation site changed: " + orig
+    r = _run_pin(tmp_path, name, open(SRC).read(), pin, src3f_text=src3f.replace(orig, repl))
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
