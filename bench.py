@@ -151,6 +151,61 @@ def run3d(args, copy_gbs):
     print(json.dumps(out), flush=True)
 
 
+def run3f(args, copy_gbs):
+    """The 3f model (two CH lattices, phi0 evolving) on drops in layers."""
+    import torch
+    from paper_2311_05091_amd import geometry3f as G3F
+    from paper_2311_05091_amd.lbm3f import Context3F
+    spec = G3F.drops_in_layers(n=args.n3f, n_drops=max(8, (args.n3f // 128) ** 2 // 2), rmin=12.0, rmax=48.0,
+                               rho=(2.0, 3.0, 1.0), mu=(0.2, 0.3, 0.1), sigma01=0.012, sigma02=0.008, sigma12=0.01)
+    nodes = spec.nx * spec.ny
+    wname = "drops_in_layers_3f_%dx%d" % (spec.nx, spec.ny)
+    print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)
+    ctx = Context3F(precision=args.precision)
+    ctx.add_domain(spec)
+    ctx.finalize()
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    settle_steps = 0
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        ctx.step(10)
+        settle_steps += 10
+    torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.kernel_timing(False)
+    mass = ctx.mass(0)
+    print("[bench] %d steps in %.3f s, kernel avg %.4f ms over %d launches, masses %.10e %.10e" %
+          (args.steps, dt, kern_ms, launches, mass[0], mass[1]), flush=True)
+    if not np.isfinite(mass).all():
+        raise SystemExit("bench: the 3f state is not finite after the timed steps; no figure reported")
+    bpn = ctx.bytes_per_node(0)
+    achieved = bpn * nodes / (kern_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_node": bpn,
+            "kernel_ms": round(kern_ms, 5)}
+    if copy_gbs:
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    out = {
+        "metric": METRIC, "value": round(nodes * args.steps / dt / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "settle_s": round(settle_s, 3), "settle_steps": settle_steps,
+        "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
+        "config": {"workload": wname, "nodes": nodes, "lattice": "D2Q9 x 3 (two CH + NS), 3f model",
+                   "tile": [64, 32], "precision": args.precision},
+        "roofline": roof,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +216,7 @@ def main():
     ap.add_argument("--ny", type=int, default=2048, help="porous workload height")
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--n3", type=int, default=256, help="edge of the 3D porous workload (--workload porous3d)")
+    ap.add_argument("--n3f", type=int, default=2048, help="edge of the 3f workload (--workload drops3f)")
     ap.add_argument("--tile", type=int, default=0, help="tile code; 0 = autotune (per size class for batches)")
     ap.add_argument("--tile-cache", default=None, help="JSON cache of the per-size-class autotuner")
     ap.add_argument("--launch-mode", type=int, default=0,
@@ -202,6 +258,8 @@ def main():
 
     if args.workload == "porous3d":
         return run3d(args, copy_gbs)
+    if args.workload == "drops3f":
+        return run3f(args, copy_gbs)
     specs, wname = workload(args.workload, args.nx, args.ny)
     nodes = sum(s.nx * s.ny for s in specs)
     print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)

@@ -1,7 +1,7 @@
 """Builds the HIP libraries libtpf.so and libtpf_nn.so for gfx950 with hipcc
-(in-tree).  libtpf.so is compiled from six translation units in parallel (the
-host sides of the 2D and 3D steps and their FP32 and FP64 kernel instances)
-and linked."""
+(in-tree).  libtpf.so is compiled from seven translation units in parallel
+(the host sides of the 2D and 3D steps and their FP32 and FP64 kernel
+instances, and the 3f model) and linked."""
 from __future__ import annotations
 
 import os
@@ -22,7 +22,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 COMMON = FLAGS + ["-shared"]
 LBM_SOURCES = ("tpf_api.hip", "tpf_launch_f32.hip", "tpf_launch_f64.hip", "tpf3_api.hip",
-               "tpf3_launch_f32.hip", "tpf3_launch_f64.hip")
+               "tpf3_launch_f32.hip", "tpf3_launch_f64.hip", "tpf3f_api.hip")
 
 
 def _compile(sources, out, extra=()):

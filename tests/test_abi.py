@@ -103,6 +103,54 @@ def test_tpf3_default_params():
     assert list(p.s_g) == [1.0, 1.0, 0.5, 0.5]
 
 
+def test_tpf3f_exports_every_declared_symbol_and_defaults():
+    names = header_functions(os.path.join(ROOT, "include", "tpf3f.h"))
+    assert "tpf3f_step" in names and len(names) >= 12
+    lib = _lib("libtpf.so")
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_2311_05091_amd import lbm3f
+    assert sorted(lbm3f.EXPORTED3F) == names
+    lib = lbm3f.library3f()
+    p = lbm3f.DomainParams3F()
+    lib.tpf3f_default_params(ctypes.byref(p), 40, 30)
+    assert (p.nx, p.ny, p.periodic_x, p.periodic_y) == (40, 30, 1, 0)
+    assert p.sigma01 == p.sigma02 == p.sigma12 == 0.01 and p.d0 == 0.5 and p.M_deg == 0.01
+
+
+def test_tpf3f_rejects_parameters_without_device():
+    """Validation of a 3f domain needs no device: a non-positive gamma_p (one
+    tension above the sum of the other two), tau_phi <= 1/2, a rate outside
+    (0, 2) and a 2 x 3 domain are rejected; a valid one gives an arena size."""
+    import numpy as np
+    from paper_2311_05091_amd import lbm3f
+    lib = lbm3f.library3f()
+    h = ctypes.c_void_p()
+    assert lib.tpf3f_create(ctypes.byref(h), 32, None) == 0
+    z = np.zeros((12, 10))
+    did = ctypes.c_int32()
+    EINVAL = -1
+
+    def add(**kw):
+        p = lbm3f.DomainParams3F()
+        lib.tpf3f_default_params(ctypes.byref(p), 10, 12)
+        for k, v in kw.items():
+            if k == "s_g0":
+                p.s_g[0] = v
+            else:
+                setattr(p, k, v)
+        return lib.tpf3f_add_domain(h, ctypes.byref(p), z.ctypes.data_as(lbm3f._D), z.ctypes.data_as(lbm3f._D),
+                                    ctypes.byref(did))
+    assert add(sigma01=0.03) == EINVAL
+    assert add(tau_phi=0.5) == EINVAL
+    assert add(s_g0=2.0) == EINVAL
+    assert add(nx=2) == EINVAL
+    assert add() == 0
+    nb = ctypes.c_uint64()
+    assert lib.tpf3f_arena_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 54 * 4 * 120
+    lib.tpf3f_destroy(h)
+
+
 def test_library_constants_match_oracle_without_device(orc):
     """A context needs no device until tpf_finalize: the library's per-domain
     constants (spreading factor k, gamma_p, gamma^T, eta; Sec. 2.2-3) equal the
