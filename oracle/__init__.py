@@ -50,6 +50,8 @@ class Params(C.Structure):
         ("Fb", C.c_double * 2), ("u_wall", C.c_double * 2),
         ("omega_wall", C.c_double), ("wall_center", C.c_double * 2),
         ("rho_gauge", C.c_double),
+        ("open_x", C.c_int32), ("inlet_type", C.c_int32),
+        ("p_in", C.c_double), ("u_in", C.c_double), ("p_out", C.c_double), ("phi1_in", C.c_double),
     ]
 
 
@@ -106,6 +108,7 @@ def _lib_handle():
         lib.orc_step.argtypes = [C.c_void_p, C.c_int64]
         lib.orc_moments.argtypes = [C.c_void_p, _D, _D, _D, _D]
         lib.orc_aux.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.orc_flow_rates.argtypes = [C.c_void_p, _D]
         lib.orc_mass.restype = C.c_double
         lib.orc_mass.argtypes = [C.c_void_p]
         lib.orc_step_count.restype = C.c_int64
@@ -201,7 +204,8 @@ def make_params(nx, ny, *, periodic_x=1, periodic_y=0, d0=0.5, D=4.0, sigma12=0.
                 theta_deg=60.0, kappa=0.0, rho=(1.0, 1.0, 1.0), mu=(0.15, 0.15, 0.15),
                 M_cst=0.0, M_deg=0.1, tau_phi=0.8, s_phi=(1.0, 1.0, 1.0, 1.0),
                 s_g=(1.0, 1.0, 1.0, 1.0), Fb=(0.0, 0.0), u_wall=(0.0, 0.0),
-                omega_wall=0.0, wall_center=(0.0, 0.0), rho_gauge=0.0) -> Params:
+                omega_wall=0.0, wall_center=(0.0, 0.0), rho_gauge=0.0, open_x=0, inlet_type=0,
+                p_in=0.0, u_in=0.0, p_out=0.0, phi1_in=0.0) -> Params:
     p = Params()
     p.nx, p.ny, p.periodic_x, p.periodic_y = nx, ny, periodic_x, periodic_y
     p.d0, p.D, p.sigma12 = d0, D, sigma12
@@ -216,6 +220,8 @@ def make_params(nx, ny, *, periodic_x=1, periodic_y=0, d0=0.5, D=4.0, sigma12=0.
     p.omega_wall = omega_wall
     p.wall_center[:] = list(wall_center)
     p.rho_gauge = rho_gauge
+    p.open_x, p.inlet_type = open_x, inlet_type
+    p.p_in, p.u_in, p.p_out, p.phi1_in = p_in, u_in, p_out, phi1_in
     return p
 
 
@@ -368,6 +374,12 @@ class Sim:
 
     def mass(self) -> float:
         return _lib_handle().orc_mass(self._h)
+
+    def flow_rates(self):
+        """Sums over phi0 <= 1/2 of u_x, phi1 u_x, phi2 u_x (current level)."""
+        q = np.zeros(3)
+        _lib_handle().orc_flow_rates(self._h, _ptr(q))
+        return q
 
     def get_state(self):
         n = self.nx * self.ny

@@ -42,6 +42,10 @@
  *       where its coefficient is zero (d0 = 1/2) and where s2a = 0 (a saturated
  *       solid node, phi0 = 1: its second-order NS moments do not relax, and
  *       the relation for p holds no finite value of the term).
+ *   R27 open boundaries (Sec. 4 names non-equilibrium extrapolation for
+ *       velocity and pressure boundaries): applied after the collision to
+ *       the inlet column x = 0 and outlet column x = nx - 1 with the inner
+ *       neighbour's non-equilibrium part (see open_boundaries).
  *   R19 the solid-point velocity u_w of f = (u_w - u*)/dt (Sec. 3) is that of a
  *       rigid body: u_w(x) = u_wall + omega_wall e_z x (x - wall_center), with
  *       the solid field phi0 held fixed (a solid whose shape is invariant under
@@ -74,6 +78,10 @@ typedef struct {
     double omega_wall;  /* angular velocity of the solid about wall_center */
     double wall_center[2];
     double rho_gauge;   /* constant in lambda_0                           */
+    int32_t open_x;     /* 1: inlet at x = 0, outlet at x = nx - 1 (R27)  */
+    int32_t inlet_type; /* 0: pressure p_in, 1: velocity (u_in, 0)        */
+    double p_in, u_in, p_out;
+    double phi1_in;     /* phase-1 share of the fluid entering (x (1 - phi0)) */
 } orc_params;
 
 typedef struct {
@@ -379,7 +387,7 @@ typedef struct {
 } orc_sim;
 
 enum { F_PHI1, F_LAP0, F_GX0, F_GY0, F_LAP1, F_GX1, F_GY1, F_MU0, F_MU1, F_MU2,
-       F_MUB, F_GMX, F_GMY, F_UX, F_UY, F_P, NF };
+       F_MUB, F_GMX, F_GMY, F_UX, F_UY, F_P, F_SX, F_SY, NF };
 
 #define FLD(s, k) ((s)->fld + (size_t)(k) * (s)->n)
 
@@ -548,6 +556,8 @@ static void macro_and_collide(orc_sim* s, int collide)
             FLD(s, F_UX)[id] = ux;
             FLD(s, F_UY)[id] = uy;
             FLD(s, F_P)[id] = p;
+            FLD(s, F_SX)[id] = Sx;
+            FLD(s, F_SY)[id] = Sy;
             if (!collide) continue;
 
             /* ---- CH collision ---- */
@@ -589,6 +599,65 @@ static void macro_and_collide(orc_sim* s, int collide)
     if (collide) memcpy(s->lag, lag_new, 7 * n * sizeof(double));
 }
 
+/* Open boundaries in x by non-equilibrium extrapolation (Sec. 4, reading
+ * R27): after the collision, the populations of a boundary node b (x = 0,
+ * the inlet; x = nx - 1, the outlet) are its equilibrium at the boundary
+ * values plus the non-equilibrium part of its inner neighbour n (x = 1,
+ * x = nx - 2) at this step:  f*_i(b) = f^eq_i(b) + f*_i(n) - f^eq_i(n), and
+ * the same for g.  Boundary values: inlet phi1 = phi1_in (1 - phi0), mubar1
+ * = 0, S = 0, and either p = p_in with u from n or u = (u_in, 0) with p from
+ * n; outlet p = p_out with phi1, mubar1, u, S from n.  The lagged fields of b
+ * are set from the same values. */
+static void open_boundaries(orc_sim* s)
+{
+    const orc_params* P = &s->P;
+    const int nx = s->nx, ny = s->ny;
+    const size_t n = s->n;
+    const double r0 = P->rho[0], r1 = P->rho[1], r2 = P->rho[2];
+    for (int y = 0; y < ny; ++y)
+        for (int side = 0; side < 2; ++side) {
+            const size_t ib = (size_t)y * nx + (side ? nx - 1 : 0);
+            const size_t in = (size_t)y * nx + (side ? nx - 2 : 1);
+            const double p0n = s->phi0[in], p1n = FLD(s, F_PHI1)[in], mbn = FLD(s, F_MUB)[in];
+            const double uxn = FLD(s, F_UX)[in], uyn = FLD(s, F_UY)[in], pn = FLD(s, F_P)[in];
+            const double Sxn = FLD(s, F_SX)[in], Syn = FLD(s, F_SY)[in];
+            const double rhon = r0 * p0n + r1 * p1n + r2 * (1.0 - p0n - p1n);
+            const double p0b = s->phi0[ib];
+            double p1b, mbb, uxb, uyb, pb, Sxb, Syb;
+            if (side == 0) {
+                p1b = P->phi1_in * (1.0 - p0b);
+                mbb = 0.0;
+                Sxb = Syb = 0.0;
+                if (P->inlet_type == 0) { pb = P->p_in; uxb = uxn; uyb = uyn; }
+                else { pb = pn; uxb = P->u_in; uyb = 0.0; }
+            } else {
+                p1b = p1n; mbb = mbn; pb = P->p_out; uxb = uxn; uyb = uyn; Sxb = Sxn; Syb = Syn;
+            }
+            const double rhob = r0 * p0b + r1 * p1b + r2 * (1.0 - p0b - p1b);
+            double feb[9], fen[9], geb[9], gen[9];
+            orc_feq(P->d0, p1b, s->d.eta * mbb, p1b * uxb, p1b * uyb, feb);
+            orc_feq(P->d0, p1n, s->d.eta * mbn, p1n * uxn, p1n * uyn, fen);
+            orc_geq(P->d0, P->rho_gauge, pb, rhob, uxb, uyb, Sxb, Syb, geb);
+            orc_geq(P->d0, P->rho_gauge, pn, rhon, uxn, uyn, Sxn, Syn, gen);
+            for (int i = 0; i < 9; ++i) {
+                s->fpost[(size_t)i * n + ib] = feb[i] + s->fpost[(size_t)i * n + in] - fen[i];
+                s->gpost[(size_t)i * n + ib] = geb[i] + s->gpost[(size_t)i * n + in] - gen[i];
+            }
+            s->lag[0 * n + ib] = p1b * uxb;
+            s->lag[1 * n + ib] = p1b * uyb;
+            s->lag[2 * n + ib] = (rhob * uxb - Sxb) * uxb + (rhob * uyb - Syb) * uyb;
+            s->lag[3 * n + ib] = Sxb * uxb;
+            s->lag[4 * n + ib] = Syb * uyb;
+            s->lag[5 * n + ib] = 0.5 * (Sxb * uyb + Syb * uxb);
+            s->lag[6 * n + ib] = Sxb * uyb - Syb * uxb;
+        }
+}
+
+/* Sums over the pore space (phi0 <= 1/2) of u_x, phi1 u_x and phi2 u_x at
+ * the current time level: the integrals of the relative permeability
+ * K_p (Sec. 4.6), with u_{x,p} read as phi_p u_x. */
+void orc_flow_rates(orc_sim* s, double q[3]);
+
 /* ---------------------------------------------------------------------- */
 /* Public entry points (called through ctypes by the tests)                */
 /* ---------------------------------------------------------------------- */
@@ -596,7 +665,7 @@ orc_sim* orc_create(const orc_params* P, const double* phi0, const double* phi1)
 {
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->P = *P;
-    if (orc_derive(P, &s->d) != 0) { free(s); return NULL; }
+    if (orc_derive(P, &s->d) != 0 || (P->open_x && P->periodic_x)) { free(s); return NULL; }
     s->nx = P->nx; s->ny = P->ny; s->n = (size_t)P->nx * P->ny;
     size_t n = s->n;
     s->phi0 = (double*)malloc(n * sizeof(double));
@@ -654,6 +723,7 @@ void orc_step(orc_sim* s, int64_t nsteps)
     for (int64_t k = 0; k < nsteps; ++k) {
         stream(s);
         macro_and_collide(s, 1);
+        if (s->P.open_x) open_boundaries(s);
         s->step++;
     }
 }
@@ -718,4 +788,21 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+void orc_flow_rates(orc_sim* s, double q[3])
+{
+    stream(s);
+    macro_and_collide(s, 0);
+    long double a = 0.0L, b = 0.0L, c = 0.0L;
+    for (size_t id = 0; id < s->n; ++id) {
+        if (s->phi0[id] > 0.5) continue;
+        const double ux = FLD(s, F_UX)[id], p1 = FLD(s, F_PHI1)[id];
+        a += ux;
+        b += p1 * ux;
+        c += (1.0 - s->phi0[id] - p1) * ux;
+    }
+    q[0] = (double)a;
+    q[1] = (double)b;
+    q[2] = (double)c;
 }

@@ -46,6 +46,12 @@ class DomainSpec:
     omega_wall: float = 0.0
     wall_center: tuple = (0.0, 0.0)
     rho_gauge: float = 0.0
+    open_x: int = 0          # 1: inlet at x = 0, outlet at x = nx - 1 (needs periodic_x = 0)
+    inlet_type: int = 0      # 0: pressure p_in, 1: velocity (u_in, 0)
+    p_in: float = 0.0
+    u_in: float = 0.0
+    p_out: float = 0.0
+    phi1_in: float = 0.0     # phase-1 share of the fluid entering at the inlet
     name: str = ""
 
     def param_dict(self) -> dict:

@@ -7,7 +7,8 @@ def oracle_params(orc, sp, **kw):
              sigma12=sp.sigma12, theta_deg=sp.theta_deg, kappa=sp.kappa, rho=sp.rho, mu=sp.mu,
              M_cst=sp.M_cst, M_deg=sp.M_deg, tau_phi=sp.tau_phi, s_phi=sp.s_phi, s_g=sp.s_g,
              Fb=sp.Fb, u_wall=sp.u_wall, omega_wall=sp.omega_wall,
-             wall_center=sp.wall_center, rho_gauge=sp.rho_gauge)
+             wall_center=sp.wall_center, rho_gauge=sp.rho_gauge, open_x=sp.open_x, inlet_type=sp.inlet_type,
+             p_in=sp.p_in, u_in=sp.u_in, p_out=sp.p_out, phi1_in=sp.phi1_in)
     d.update(kw)
     return orc.make_params(sp.nx, sp.ny, **d)
 

@@ -26,6 +26,9 @@ SPIN = "tests/test_oracle_solid.py::test_spinning_cavity_rigid_rotation"
 NORMAL3 = "tests/test_oracle3d.py::test_translating_interface_3d_density_ratio_10"
 TANGENT3 = "tests/test_oracle3d.py::test_tangential_flow_along_relaxing_interface_3d"
 LAPLACE3 = "tests/test_oracle3d.py::test_laplace_law_sphere"
+POIS_OPEN = "tests/test_oracle_open.py::test_pressure_driven_channel_is_poiseuille"
+VEL_OPEN = "tests/test_oracle_open.py::test_velocity_inlet_conserves_flux"
+LAYERS = "tests/test_oracle_open.py::test_stratified_two_phase_flow_rates_and_kp"
 RELABEL3F = "tests/test_oracle_3f.py::test_3f_exchanging_phases_0_and_1"
 LAPLACE3F = "tests/test_oracle_3f.py::test_3f_laplace_law_for_phase_0_in_phase_2"
 LENS3F = "tests/test_oracle_3f.py::test_3f_lens_corner_angles_follow_neumann_triangle"
@@ -56,6 +59,13 @@ MUTANTS = [
      SLIDE),
     ("wall_velocity_half", "double fsx = uwx - usx", "double fsx = 0.5 * uwx - usx", SLIDE),
     ("rotation_sign", "double uwy = P->u_wall[1] + P->omega_wall", "double uwy = P->u_wall[1] - P->omega_wall", SPIN),
+    ("open_g_equilibrium_only", "s->gpost[(size_t)i * n + ib] = geb[i] + s->gpost[(size_t)i * n + in] - gen[i];",
+     "s->gpost[(size_t)i * n + ib] = geb[i];", POIS_OPEN),
+    ("open_inlet_pressure_from_neighbour", "if (P->inlet_type == 0) { pb = P->p_in;",
+     "if (P->inlet_type == 0) { pb = pn;", POIS_OPEN),
+    ("open_inlet_velocity_from_neighbour", "else { pb = pn; uxb = P->u_in; uyb = 0.0; }",
+     "else { pb = pn; uxb = uxn; uyb = uyn; }", VEL_OPEN),
+    ("flow_rate_phase1_unweighted", "b += p1 * ux;", "b += ux;", LAYERS),
 ]
 
 # mistakes planted in the three-dimensional oracle
