@@ -70,6 +70,16 @@ typedef struct {
     double omega_wall;            /* angular velocity of the solid; 0                   */
     double wall_center[2];        /* centre of that rotation; 0                         */
     double rho_gauge;             /* constant in lambda_0 (Sec. 3); 0 = offset storage   */
+    int32_t open_x;               /* 1: open ends in x, an inlet at x = 0 and an outlet at
+                                     x = nx - 1, imposed after each collision by
+                                     non-equilibrium extrapolation from the inner
+                                     neighbour (Sec. 4); needs periodic_x = 0; 0      */
+    int32_t inlet_type;           /* 0: pressure inlet p_in (u extrapolated), 1: velocity
+                                     inlet (u_in, 0) (p extrapolated); 0               */
+    double p_in, u_in, p_out;     /* inlet pressure or velocity, outlet pressure; 0      */
+    double phi1_in;               /* phase-1 share of the fluid entering: phi1 = phi1_in
+                                     (1 - phi0) at the inlet, mubar1 = 0 there; the outlet
+                                     takes phi1 and mubar1 from its neighbour; 0       */
 } tpf_domain_params;
 
 typedef struct tpf_ctx tpf_ctx;
@@ -121,6 +131,13 @@ int tpf_run_to_residual(tpf_ctx* ctx, double tol, int32_t check_every, int64_t m
  * u (with the solid correction u = u* + phi0 f/2) and p (Sec. 3).  Host
  * arrays of nx*ny float64; any may be NULL. */
 int tpf_read_moments(tpf_ctx* ctx, int32_t id, double* phi1, double* ux, double* uy, double* p);
+
+/* Flow rates of domain id at the current time level over its pore space
+ * (phi0 <= 1/2): q[0] = sum u_x, q[1] = sum phi1 u_x, q[2] = sum phi2 u_x,
+ * FP64 compensated.  The relative permeability of fluid p (Sec. 4.6) is
+ * q[p] of a two-phase run over q[0] of a single-phase run of fluid p under
+ * the same drive. */
+int tpf_flow_rates(tpf_ctx* ctx, int32_t id, double* q);
 
 /* Diagnostics of domain id from the last reduction: mass = sum phi1 (FP64,
  * compensated), residual as in tpf_run_to_residual (NaN before two checks),
@@ -195,7 +212,8 @@ int tpf_domain_tile(tpf_ctx* ctx, int32_t id, int32_t* code);
  * step over all live domains' tiles; 1 = one persistent launch per call that
  * advances all live domains through the steps: a work queue of (step, tile)
  * items with a per-domain barrier between steps (device-scope counters).
- * Mode 1 applies to the strip tile codes 8-10; with any other tile code the
+ * Mode 1 applies to the strip tile codes 8-10 and to batches without open
+ * ends; with any other tile code or an open domain the
  * calls fall back to one launch per step.  Both modes give the same state.
  * A barrier wait that exceeds its spin bound (it cannot in a correct run)
  * makes the call return TPF_EDEVICE.  2 = one launch per step with the tile

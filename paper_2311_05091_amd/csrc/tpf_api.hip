@@ -80,6 +80,8 @@ struct tpf_ctx {
     DomDev* d_doms = nullptr;
     int4* d_tiles = nullptr;
     int* d_domlist = nullptr;
+    int* d_open = nullptr;       // ids of the domains with open ends in x
+    int n_open = 0;
     double* d_partials = nullptr;
     double* d_red = nullptr;   // [ndom][4]
     double* d_scratch = nullptr;  // max(4 N, 18 N) doubles
@@ -194,6 +196,10 @@ static int validate(const tpf_domain_params& p) {
     if (!std::isfinite(p.omega_wall) || !std::isfinite(p.wall_center[0]) || !std::isfinite(p.wall_center[1]) ||
         !std::isfinite(p.u_wall[0]) || !std::isfinite(p.u_wall[1]))
         return TPF_EINVAL;
+    if (p.open_x != 0 && p.open_x != 1) return TPF_EINVAL;
+    if (p.open_x && (p.periodic_x || p.nx < 4 || (p.inlet_type != 0 && p.inlet_type != 1))) return TPF_EINVAL;
+    if (!std::isfinite(p.p_in) || !std::isfinite(p.u_in) || !std::isfinite(p.p_out) || !std::isfinite(p.phi1_in))
+        return TPF_EINVAL;
     double k, g[3], gT;
     derive_gamma(p, k, g, gT);
     if (!(g[0] > 0 && g[1] > 0 && g[2] > 0)) return TPF_EINVAL;
@@ -255,6 +261,10 @@ static void fill_kconst(const tpf_domain_params& p, const HostDomain& h, KConst<
     K.Kp = (T)(1.0 - c2);
     K.AH = (T)((1.0 - c2) / p.s_g[0] + 0.5 * (1.0 - 3.0 * c2));
     K.BH = (T)(2.0 - 4.0 * c2);
+    K.p_in = (T)p.p_in;
+    K.u_in = (T)p.u_in;
+    K.p_out = (T)p.p_out;
+    K.phi1_in = (T)p.phi1_in;
 }
 
 static void fill_constants(HostDomain& h) {
@@ -269,6 +279,8 @@ static void fill_constants(HostDomain& h) {
     d.py = p.periodic_y ? 1 : 0;
     d.has_s = (p.rho[1] != p.rho[2]) ? 1 : 0;
     d.bh_zero = (2.0 - 4.0 * p.d0 == 0.0) ? 1 : 0;
+    d.open_x = p.open_x ? 1 : 0;
+    d.inlet_type = p.inlet_type;
     fill_kconst<double>(p, h, d.kd);
     fill_kconst<float>(p, h, d.kf);
 }
@@ -287,6 +299,7 @@ static size_t domain_bytes(const HostDomain& h, int prec) {
     b += align_up(N * e, 256);               // B
     if (S) b += align_up(3 * N * e, 256) + align_up(2 * N * e, 256);  // C, psi[2]
     b += align_up(N * 8, 256);               // snap (float64)
+    if (h.p.open_x) b += align_up(2 * kBndFields * (size_t)h.p.ny * e, 256);  // bnd
     return b;
 }
 
@@ -318,6 +331,7 @@ static size_t total_bytes(tpf_ctx* c) {
     b += align_up(nd * sizeof(DomDev), 256);
     b += align_up(mt * sizeof(int4), 256);
     b += align_up(nd * sizeof(int), 256);
+    b += align_up(nd * sizeof(int), 256);  // open-domain list
     b += align_up(nd * kRedMaxBlocks * 7 * sizeof(double), 256);
     b += align_up(nd * 4 * sizeof(double), 256);
     b += align_up(18 * max_nodes(c) * sizeof(double), 256);
@@ -397,7 +411,7 @@ static int refresh_live(tpf_ctx* c) {
 
 // The persistent launch runs one strip code (8-10) for every live domain.
 static bool persistent_ok(const tpf_ctx* c) {
-    if (c->launch_mode != 1 || c->groups.empty()) return false;
+    if (c->launch_mode != 1 || c->groups.empty() || c->n_open > 0) return false;
     const int code = c->groups[0].code;
     for (const TileGroup& g : c->groups)
         if (g.code != code) return false;
@@ -486,6 +500,22 @@ static void adapt_tile(tpf_ctx* c) {
     c->tile_code = pick;
 }
 
+// Non-equilibrium extrapolation at the open ends of every open domain, after
+// the step launched with the same step offset.
+static hipError_t launch_open_bc(tpf_ctx* c, int offset) {
+    int maxny = 1;
+    for (auto& h : c->doms)
+        if (h.p.open_x) maxny = std::max(maxny, h.p.ny);
+    const dim3 grid((unsigned)((2 * maxny + 255) / 256), (unsigned)c->n_open);
+    if (c->precision == 32)
+        hipLaunchKernelGGL(open_bc_kernel<float>, grid, dim3(256), 0, c->stream, c->d_doms, c->d_open, c->n_open,
+                           offset);
+    else
+        hipLaunchKernelGGL(open_bc_kernel<double>, grid, dim3(256), 0, c->stream, c->d_doms, c->d_open, c->n_open,
+                           offset);
+    return hipGetLastError();
+}
+
 static int run_steps(tpf_ctx* c, int64_t n) {
     if (n <= 0) return TPF_OK;
     if (c->launch_mode == 2) adapt_tile(c);
@@ -510,7 +540,10 @@ static int run_steps(tpf_ctx* c, int64_t n) {
         HIP_OK(hipEventCreate(&tb));
         HIP_OK(hipEventRecord(ta, c->stream));
     }
-    for (int64_t s = 0; s < n; ++s) HIP_OK(launch_step(c, kModeStep, c->groups, (int)(s & 1), nullptr));
+    for (int64_t s = 0; s < n; ++s) {
+        HIP_OK(launch_step(c, kModeStep, c->groups, (int)(s & 1), nullptr));
+        if (c->n_open > 0) HIP_OK(launch_open_bc(c, (int)(s & 1)));
+    }
     if (c->timing) {
         HIP_OK(hipEventRecord(tb, c->stream));
         c->ev_pool.push_back(ta);
@@ -678,6 +711,7 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
             d.psi[0] = d.psi[1] = nullptr;
         }
         d.snap = (double*)take(N * 8);
+        d.bnd = h.p.open_x ? take(2 * kBndFields * (size_t)h.p.ny * e) : nullptr;
         d.parity = 0;
         d.live = 1;
     }
@@ -686,6 +720,7 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
     c->d_doms = (DomDev*)take(nd * sizeof(DomDev));
     c->d_tiles = (int4*)take(c->max_tiles * sizeof(int4));
     c->d_domlist = (int*)take(nd * sizeof(int));
+    c->d_open = (int*)take(nd * sizeof(int));
     c->d_partials = (double*)take(nd * kRedMaxBlocks * 7 * sizeof(double));
     c->d_red = (double*)take(nd * 4 * sizeof(double));
     c->d_scratch = (double*)take(18 * max_nodes(c) * sizeof(double));
@@ -700,6 +735,15 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
         HIP_OK(hipGetDeviceProperties(&prop, dev));
         c->n_cu = prop.multiProcessorCount;
         c->device = std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount);
+    }
+    {
+        std::vector<int> open;
+        for (size_t i = 0; i < c->doms.size(); ++i)
+            if (c->doms[i].p.open_x) open.push_back((int)i);
+        c->n_open = (int)open.size();
+        if (!open.empty())
+            HIP_OK(hipMemcpyAsync(c->d_open, open.data(), open.size() * sizeof(int), hipMemcpyHostToDevice,
+                                  c->stream));
     }
     int rc = upload_descriptors(c);
     if (rc) return rc;
@@ -790,6 +834,32 @@ extern "C" int tpf_read_moments(tpf_ctx* c, int32_t id, double* phi1, double* ux
     return TPF_OK;
 }
 
+extern "C" int tpf_flow_rates(tpf_ctx* c, int32_t id, double* q) {
+    if (!c || !q || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
+    if (!c->finalized) return TPF_ESTATE;
+    std::vector<int4> t;
+    std::vector<TileGroup> grp;
+    std::vector<int> one = {id};
+    int rc = build_tiles(c, one, t, grp);
+    if (rc) return rc;
+    c->tiles_dirty = true;
+    HIP_OK(launch_step(c, kModeMoments, grp, 0, c->d_scratch));
+    const int N = c->doms[id].p.nx * c->doms[id].p.ny;
+    const int nblk = std::max(1, std::min(kRedMaxBlocks, (N + kRedThreads - 1) / kRedThreads));
+    if (c->precision == 32)
+        hipLaunchKernelGGL(flow_partials<float>, dim3(nblk), dim3(kRedThreads), 0, c->stream, c->d_doms, id,
+                           c->d_scratch, c->d_partials);
+    else
+        hipLaunchKernelGGL(flow_partials<double>, dim3(nblk), dim3(kRedThreads), 0, c->stream, c->d_doms, id,
+                           c->d_scratch, c->d_partials);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(flow_final, dim3(1), dim3(64), 0, c->stream, c->d_partials, nblk, c->d_red + 4 * id);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(q, c->d_red + 4 * id, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return TPF_OK;
+}
+
 extern "C" int tpf_read_diag(tpf_ctx* c, int32_t id, double* mass, double* residual, int32_t* status,
                              int64_t* steps) {
     if (!c || id < 0 || id >= (int)c->doms.size()) return TPF_EINVAL;
@@ -846,7 +916,7 @@ extern "C" int tpf_get_populations(tpf_ctx* c, int32_t id, double* f, double* g)
 
 // Checkpoint: a header, then per domain its host bookkeeping and its whole
 // arena slice (populations of both buffers, phi0, lagged fields, snapshot).
-static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '2'};
+static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '3'};
 
 static size_t domain_slice_bytes(const tpf_ctx* c, const HostDomain& h) {
     return domain_bytes(h, c->precision);

@@ -79,7 +79,13 @@ struct KConst {
                                  //                                       uwy + om (x - xc))
     T pfac, pw, Kp, AH, BH;      // p = pfac [ sum_{i>0} g_i + (1/2 + H) Q - pw B + Kp/2 dB ],
                                  // H = Kp (AH - BH/s2a)
+    T p_in, u_in, p_out, phi1_in;  // open-boundary values (inlet x = 0, outlet x = nx - 1)
 };
+
+// Fields an open domain's step stores for the columns x = 1 and x = nx - 2
+// (the inner neighbours of the inlet and outlet), for the boundary kernel:
+// bnd[side][field][y], side 0 = inlet, 1 = outlet.
+enum { kBndPhi1, kBndMub, kBndUx, kBndUy, kBndP, kBndSx, kBndSy, kBndFields };
 
 // Per-domain descriptor in device memory.  Pointers are element pointers of
 // the storage precision.
@@ -89,6 +95,7 @@ struct DomDev {
     int32_t live;                // 1 while the domain is being advanced
     int32_t has_s;               // rho1 != rho2: extra flux S, F_c and C are active
     int32_t bh_zero;             // BH == 0 (d0 = 1/2): H does not depend on s2a
+    int32_t open_x, inlet_type;  // open ends in x (inlet 0 pressure / 1 velocity)
     void* f[2];                  // [9][ny][nx] CH populations (ping-pong)
     void* g[2];                  // [9][ny][nx] NS populations (ping-pong)
     void* phi0;                  // [ny][nx] solid field
@@ -97,6 +104,7 @@ struct DomDev {
     void* lagC;                  // [3][ny][nx] sym(S u) of the previous step (has_s)
     void* psi[2];                // [ny][nx]    S_x u_y - S_y u_x (has_s, ping-pong)
     double* snap;                // [ny][nx]    phi1 at the last residual check
+    void* bnd;                   // [2][kBndFields][ny] inner-neighbour fields (open_x)
     KConst<double> kd;
     KConst<float> kf;
 };

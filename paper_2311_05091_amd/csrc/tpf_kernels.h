@@ -96,6 +96,18 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
         mom_out[3 * N + id] = double(p);
         return;
     }
+    // open ends: the inner neighbours of the inlet and outlet keep their
+    // fields of this step for the non-equilibrium extrapolation
+    if (d.open_x && (x == 1 || x == d.nx - 2)) {
+        gptr<T> bnd = gp<T>(d.bnd) + (x == 1 ? 0 : kBndFields) * d.ny + y;
+        bnd[kBndPhi1 * d.ny] = ph1;
+        bnd[kBndMub * d.ny] = mub;
+        bnd[kBndUx * d.ny] = ux;
+        bnd[kBndUy * d.ny] = uy;
+        bnd[kBndP * d.ny] = p;
+        bnd[kBndSx * d.ny] = Sx;
+        bnd[kBndSy * d.ny] = Sy;
+    }
     gptr<T> fout = gp<T>(d.f[cur ^ 1]);
     gptr<T> gout = gp<T>(d.g[cur ^ 1]);
 
@@ -865,6 +877,158 @@ static __global__ void reduce_final(const int* __restrict__ dom_list, int ndom, 
     out[dom * 4 + 1] = r.s + r.c;
     out[dom * 4 + 2] = n2.s + n2.c;
     out[dom * 4 + 3] = bad;
+}
+
+// Open ends in x by non-equilibrium extrapolation (Sec. 4): after a step,
+// the inlet (x = 0) and outlet (x = nx - 1) nodes of each open domain take
+// their equilibrium at the boundary values plus the non-equilibrium part of
+// their inner neighbour n (x = 1, x = nx - 2) of that step.  With the
+// equilibria written by their Hermite moments (the relaxation targets of the
+// collisions), f(b) = f(n) + M^-1 [h^eq(b) - h^eq(n)], the same for g.
+// Boundary values: inlet phi1 = phi1_in (1 - phi0), mubar1 = 0, S = 0, and
+// p = p_in with u from n (inlet_type 0) or u = (u_in, 0) with p from n (1);
+// outlet p = p_out, the rest from n.  The lagged fields of b are set from
+// the same values.  Grid: x over the 2 ny (side, y) pairs, y over the open
+// domains; step_offset as in the step just launched.
+template <typename T>
+__global__ void open_bc_kernel(const DomDev* __restrict__ doms, const int* __restrict__ open, int n_open,
+                               int step_offset) {
+    if ((int)blockIdx.y >= n_open) return;
+    const DomDev& d = doms[open[blockIdx.y]];
+    if (!d.live) return;
+    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * ny) return;
+    const int side = t / ny, y = t - side * ny;
+    const KConst<T> K = kconst<T>(d);
+    const T c2 = K.c2;
+    const int out = (d.parity + step_offset + 1) & 1;
+    const int ib = y * nx + (side ? nx - 1 : 0), in = y * nx + (side ? nx - 2 : 1);
+    gptr<const T> bn = gpc<T>(d.bnd) + side * kBndFields * ny + y;
+    const T p1n = bn[kBndPhi1 * ny], mbn = bn[kBndMub * ny], uxn = bn[kBndUx * ny], uyn = bn[kBndUy * ny];
+    const T pn = bn[kBndP * ny], Sxn = bn[kBndSx * ny], Syn = bn[kBndSy * ny];
+    gptr<const T> phi0 = gpc<T>(d.phi0);
+    const T p0n = phi0[in], p0b = phi0[ib];
+    T p1b, mbb, uxb, uyb, pb, Sxb, Syb;
+    if (side == 0) {
+        p1b = K.phi1_in * (T(1) - p0b);
+        mbb = T(0);
+        Sxb = Syb = T(0);
+        if (d.inlet_type == 0) {
+            pb = K.p_in;
+            uxb = uxn;
+            uyb = uyn;
+        } else {
+            pb = pn;
+            uxb = K.u_in;
+            uyb = T(0);
+        }
+    } else {
+        p1b = p1n;
+        mbb = mbn;
+        pb = K.p_out;
+        uxb = uxn;
+        uyb = uyn;
+        Sxb = Sxn;
+        Syb = Syn;
+    }
+    const T rn = K.rho0 * p0n + K.rho1 * p1n + K.rho2 * (T(1) - p0n - p1n);
+    const T rb = K.rho0 * p0b + K.rho1 * p1b + K.rho2 * (T(1) - p0b - p1b);
+    T dh[9], dp[9];
+    // CH lattice: h^eq = (phi, phi u, c2 (eta mub - phi) twice, 0, 0, 0, c2^2 (phi - eta mub))
+    {
+        const T eb = K.eta * mbb, en = K.eta * mbn;
+        dh[0] = p1b - p1n;
+        dh[1] = p1b * uxb - p1n * uxn;
+        dh[2] = p1b * uyb - p1n * uyn;
+        dh[3] = c2 * ((eb - p1b) - (en - p1n));
+        dh[4] = dh[3];
+        dh[5] = dh[6] = dh[7] = T(0);
+        dh[8] = c2 * c2 * ((p1b - eb) - (p1n - en));
+        from_hermite(dh, dp, c2);
+        gptr<T> f = gp<T>(d.f[out]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q * N + ib] = f[q * N + in] + dp[q];
+    }
+    // NS lattice: h^eq = (gauge, rho u, p + Pi_xx - c2 gauge, p + Pi_yy - c2 gauge, Pi_xy, 0, 0,
+    // c2^2 gauge - c2 p), Pi = rho uu - (Su + uS)/2; the gauge cancels in the difference
+    {
+        const T Pxxb = rb * uxb * uxb - Sxb * uxb, Pyyb = rb * uyb * uyb - Syb * uyb;
+        const T Pxyb = rb * uxb * uyb - T(0.5) * (Sxb * uyb + uxb * Syb);
+        const T Pxxn = rn * uxn * uxn - Sxn * uxn, Pyyn = rn * uyn * uyn - Syn * uyn;
+        const T Pxyn = rn * uxn * uyn - T(0.5) * (Sxn * uyn + uxn * Syn);
+        dh[0] = T(0);
+        dh[1] = rb * uxb - rn * uxn;
+        dh[2] = rb * uyb - rn * uyn;
+        dh[3] = (pb + Pxxb) - (pn + Pxxn);
+        dh[4] = (pb + Pyyb) - (pn + Pyyn);
+        dh[5] = Pxyb - Pxyn;
+        dh[6] = dh[7] = T(0);
+        dh[8] = -c2 * (pb - pn);
+        from_hermite(dh, dp, c2);
+        gptr<T> g = gp<T>(d.g[out]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q * N + ib] = g[q * N + in] + dp[q];
+    }
+    gptr<T> A = gp<T>(d.lagA);
+    A[ib] = p1b * uxb;
+    A[N + ib] = p1b * uyb;
+    gp<T>(d.lagB)[ib] = (rb * uxb - Sxb) * uxb + (rb * uyb - Syb) * uyb;
+    if (d.has_s) {
+        gptr<T> Cl = gp<T>(d.lagC);
+        Cl[ib] = Sxb * uxb;
+        Cl[N + ib] = Syb * uyb;
+        Cl[2 * N + ib] = T(0.5) * (Sxb * uyb + Syb * uxb);
+        gp<T>(d.psi[out])[ib] = Sxb * uyb - Syb * uxb;
+    }
+}
+
+// Flow rates of one domain over its pore space (phi0 <= 1/2): sums of u_x,
+// phi1 u_x and phi2 u_x (Sec. 4.6), from the moments kernel's output
+// mom = [phi1; ux; uy; p] (float64, N each).  partials: [3][2][gridDim.x]
+// compensated per block; flow_final folds them in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+flow_partials(const DomDev* __restrict__ doms, int dom, const double* __restrict__ mom,
+              double* __restrict__ partials) {
+    const DomDev& d = doms[dom];
+    const int N = d.nx * d.ny;
+    gptr<const T> phi0 = gpc<T>(d.phi0);
+    CSum a = {0, 0}, b = {0, 0}, c = {0, 0};
+    for (int id = blockIdx.x * kRedThreads + threadIdx.x; id < N; id += gridDim.x * kRedThreads) {
+        const double p0 = double(phi0[id]);
+        if (p0 > 0.5) continue;
+        const double ux = mom[N + id], p1 = mom[id];
+        csum_add(a, ux);
+        csum_add(b, p1 * ux);
+        csum_add(c, (1.0 - p0 - p1) * ux);
+    }
+    __shared__ double sh[6][kRedThreads];
+    sh[0][threadIdx.x] = a.s; sh[1][threadIdx.x] = a.c;
+    sh[2][threadIdx.x] = b.s; sh[3][threadIdx.x] = b.c;
+    sh[4][threadIdx.x] = c.s; sh[5][threadIdx.x] = c.c;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            for (int j = 0; j < 3; ++j) {
+                CSum x = {sh[2 * j][threadIdx.x], sh[2 * j + 1][threadIdx.x]};
+                csum_merge(x, CSum{sh[2 * j][o], sh[2 * j + 1][o]});
+                sh[2 * j][threadIdx.x] = x.s;
+                sh[2 * j + 1][threadIdx.x] = x.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partials[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+static __global__ void flow_final(const double* __restrict__ partials, int nblk, double* __restrict__ out) {
+    if (threadIdx.x >= 3) return;
+    CSum r = {0, 0};
+    for (int k = 0; k < nblk; ++k)
+        csum_merge(r, CSum{partials[(2 * threadIdx.x) * nblk + k], partials[(2 * threadIdx.x + 1) * nblk + k]});
+    out[threadIdx.x] = r.s + r.c;
 }
 
 // Copies the post-collision populations of one domain to float64 [2][9][N].

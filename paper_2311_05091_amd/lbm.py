@@ -41,6 +41,8 @@ class DomainParams(C.Structure):
         ("Fb", C.c_double * 2), ("u_wall", C.c_double * 2),
         ("omega_wall", C.c_double), ("wall_center", C.c_double * 2),
         ("rho_gauge", C.c_double),
+        ("open_x", C.c_int32), ("inlet_type", C.c_int32),
+        ("p_in", C.c_double), ("u_in", C.c_double), ("p_out", C.c_double), ("phi1_in", C.c_double),
     ]
 
 
@@ -85,6 +87,7 @@ def library() -> C.CDLL:
         "tpf_run_to_residual": (C.c_int, [V, C.c_double, C.c_int32, C.c_int64, _I64]),
         "tpf_read_moments": (C.c_int, [V, C.c_int32, _D, _D, _D, _D]),
         "tpf_read_diag": (C.c_int, [V, C.c_int32, _D, _D, _I32, _I64]),
+        "tpf_flow_rates": (C.c_int, [V, C.c_int32, _D]),
         "tpf_set_phi1": (C.c_int, [V, C.c_int32, _D]),
         "tpf_set_active": (C.c_int, [V, C.c_int32, C.c_int32]),
         "tpf_get_populations": (C.c_int, [V, C.c_int32, _D, _D]),
@@ -116,7 +119,8 @@ def library() -> C.CDLL:
 
 
 EXPORTED = ("tpf_default_params", "tpf_create", "tpf_add_domain", "tpf_arena_bytes", "tpf_finalize",
-            "tpf_step", "tpf_run_to_residual", "tpf_read_moments", "tpf_read_diag", "tpf_set_phi1", "tpf_set_active",
+            "tpf_step", "tpf_run_to_residual", "tpf_read_moments", "tpf_flow_rates", "tpf_read_diag", "tpf_set_phi1",
+            "tpf_set_active",
             "tpf_get_populations", "tpf_save", "tpf_load", "tpf_set_tile", "tpf_get_tile",
             "tpf_tile_codes", "tpf_autotune", "tpf_size_class", "tpf_autotune_classes", "tpf_domain_tile",
             "tpf_set_launch_mode", "tpf_bytes_per_node",
@@ -173,6 +177,8 @@ def params_from_spec(spec: DomainSpec) -> DomainParams:
     p.omega_wall = spec.omega_wall
     p.wall_center[:] = list(spec.wall_center)
     p.rho_gauge = spec.rho_gauge
+    p.open_x, p.inlet_type = int(spec.open_x), int(spec.inlet_type)
+    p.p_in, p.u_in, p.p_out, p.phi1_in = spec.p_in, spec.u_in, spec.p_out, spec.phi1_in
     return p
 
 
@@ -265,6 +271,12 @@ class Context:
         out = [np.empty((s.ny, s.nx)) for _ in range(4)]
         _check(self.lib.tpf_read_moments(self._h, did, *[_dptr(a) for a in out]), "tpf_read_moments")
         return tuple(out)
+
+    def flow_rates(self, did: int = 0) -> np.ndarray:
+        """Sums over phi0 <= 1/2 of u_x, phi1 u_x, phi2 u_x (tpf_flow_rates)."""
+        q = np.zeros(3)
+        _check(self.lib.tpf_flow_rates(self._h, did, _dptr(q)), "tpf_flow_rates")
+        return q
 
     def diag(self, did: int = 0) -> dict:
         m, r = C.c_double(), C.c_double()

