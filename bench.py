@@ -221,6 +221,10 @@ def main():
     ap.add_argument("--tile-cache", default=None, help="JSON cache of the per-size-class autotuner")
     ap.add_argument("--launch-mode", type=int, default=0,
                     help="0: one launch per step; 1: one persistent launch for all steps (strip tiles)")
+    ap.add_argument("--to-residual", type=float, default=0.0,
+                    help="> 0: run the batch from its initial state to this residual (run_to_residual, "
+                         "at most --steps steps) and report the wall time instead of the step rate")
+    ap.add_argument("--check-every", type=int, default=100, help="residual check interval for --to-residual")
     ap.add_argument("--settle-s", type=float, default=0.3,
                     help="seconds of untimed steps run right before the timed region, after the "
                          "warmup steps: after an idle gap of even 50 ms the device runs the first "
@@ -261,6 +265,8 @@ def main():
     if args.workload == "drops3f":
         return run3f(args, copy_gbs)
     specs, wname = workload(args.workload, args.nx, args.ny)
+    if args.to_residual > 0:
+        return run_residual(args, specs, wname)
     nodes = sum(s.nx * s.ny for s in specs)
     print("[bench] workload %s, %d nodes, precision %d" % (wname, nodes, args.precision), flush=True)
     ctx = Context(precision=args.precision)
@@ -335,6 +341,52 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline: oracle, %d steps" % args.cpu_steps, flush=True)
         out["cpu_baseline"] = cpu_baseline(specs[0], args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def run_residual(args, specs, wname):
+    """Wall time of one run_to_residual call over the whole batch from its
+    initial state: every domain steps until its residual falls below the
+    tolerance (checked every --check-every steps) or --steps steps have run.
+    A first context of the same batch warms the kernels up."""
+    import torch
+    from paper_2311_05091_amd.lbm import Context
+
+    def make():
+        ctx = Context(precision=args.precision)
+        for s in specs:
+            ctx.add_domain(s)
+        ctx.finalize()
+        if args.tile:
+            ctx.set_tile(args.tile)
+        elif args.launch_mode == 0:
+            ctx.autotune_classes(steps=10, cache_path=args.tile_cache)
+        if args.launch_mode:
+            ctx.set_launch_mode(args.launch_mode)
+        return ctx
+
+    warm = make()
+    warm.run_to_residual(args.to_residual, check_every=args.check_every, max_steps=max(args.warmup, 1))
+    warm.close()
+    ctx = make()
+    code, tx, ty = ctx.tile()
+    print("[bench] %s to residual %.1e, check every %d, at most %d steps, tile %d, launch mode %d"
+          % (wname, args.to_residual, args.check_every, args.steps, code, args.launch_mode), flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, steps = ctx.run_to_residual(args.to_residual, check_every=args.check_every, max_steps=args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    node_steps = sum(s.nx * s.ny * int(n) for s, n in zip(specs, steps))
+    retired = sum(1 for n in steps if n < args.steps)
+    out = {"metric": "batch wall time to residual", "value": round(dt, 4), "unit": "s",
+           "higher_is_better": False, "rc": int(rc), "domains": len(specs), "retired": retired,
+           "steps_min": int(min(steps)), "steps_max": int(max(steps)),
+           "node_updates_per_s": round(node_steps / dt, 1),
+           "config": {"workload": wname, "tol": args.to_residual, "check_every": args.check_every,
+                      "max_steps": args.steps, "tile": code, "precision": args.precision,
+                      "launch_mode": args.launch_mode}}
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

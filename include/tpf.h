@@ -212,9 +212,14 @@ int tpf_domain_tile(tpf_ctx* ctx, int32_t id, int32_t* code);
  * step over all live domains' tiles; 1 = one persistent launch per call that
  * advances all live domains through the steps: a work queue of (step, tile)
  * items with a per-domain barrier between steps (device-scope counters).
- * Mode 1 applies to the strip tile codes 8-10 and to batches without open
- * ends; with any other tile code or an open domain the
- * calls fall back to one launch per step.  Both modes give the same state.
+ * Under tpf_run_to_residual the residual checks run inside the launch (one
+ * check item per live domain every check_every steps and at the last step)
+ * and a converged or non-finite domain leaves the queue there, with the same
+ * statuses, step counts and residuals as in mode 0.  Mode 1 applies when
+ * every live domain runs one of the strip codes 8-10 or strip-group codes
+ * 17, 20-24 and no domain has open ends; otherwise the calls fall back to
+ * one launch per step.  Both modes give the same state up to the rounding
+ * of separately compiled kernels.
  * A barrier wait that exceeds its spin bound (it cannot in a correct run)
  * makes the call return TPF_EDEVICE.  2 = one launch per step with the tile
  * shape re-chosen at every call (and every residual check) from the live

@@ -91,7 +91,9 @@ struct tpf_ctx {
     bool tuned = false;
     int launch_mode = 0;
     // persistent launcher state (inside the arena)
-    int* d_ctl = nullptr;        // [2]: next item, failure flag
+    int* d_ctl = nullptr;        // [3]: next item, failure flag, domains still live
+    int* d_retired = nullptr;    // [ndom] call-relative step at which a domain left (-1: live)
+    int* d_lastchk = nullptr;    // [ndom] call-relative step of its last residual check
     int* d_done = nullptr;       // [ndom]
     int* d_dom_tiles = nullptr;  // [ndom]
     int n_cu = 0;
@@ -335,7 +337,7 @@ static size_t total_bytes(tpf_ctx* c) {
     b += align_up(nd * kRedMaxBlocks * 7 * sizeof(double), 256);
     b += align_up(nd * 4 * sizeof(double), 256);
     b += align_up(18 * max_nodes(c) * sizeof(double), 256);
-    b += align_up(2 * sizeof(int), 256) + 2 * align_up(nd * sizeof(int), 256);
+    b += align_up(3 * sizeof(int), 256) + 4 * align_up(nd * sizeof(int), 256);
     return b;
 }
 
@@ -409,58 +411,101 @@ static int refresh_live(tpf_ctx* c) {
     return TPF_OK;
 }
 
-// The persistent launch runs one strip code (8-10) for every live domain.
+// The persistent launch runs one tile code with a persistent form (strips
+// 8-10, groups 17, 20-24) for every live domain, and no open ends.
 static bool persistent_ok(const tpf_ctx* c) {
     if (c->launch_mode != 1 || c->groups.empty() || c->n_open > 0) return false;
     const int code = c->groups[0].code;
     for (const TileGroup& g : c->groups)
         if (g.code != code) return false;
-    return code == 8 || code == 9 || code == 10;
+    return persistent_code(code);
 }
 
-// n steps of all live domains in persistent launches (chunks fit the
-// 32-bit item counter); returns TPF_EDEVICE if a wait ever timed out.
-static int run_persistent(tpf_ctx* c, int64_t n) {
-    const int ntiles = (int)c->tiles.size();
-    std::vector<int> per(c->doms.size(), 0);
-    for (const int4& t : c->tiles) per[t.x]++;
-    HIP_OK(hipMemcpyAsync(c->d_dom_tiles, per.data(), per.size() * sizeof(int), hipMemcpyHostToDevice,
-                          c->stream));
-    bool S = false;  // some live domain has S: the S-capable instance
-    for (const TileGroup& g : c->groups) S = S || g.s;
-    const int code = c->groups[0].code;
-    const int64_t max_chunk = std::max<int64_t>(2, ((int64_t)1 << 30) / std::max(ntiles, 1));
+// n steps of all live domains in persistent launches (chunks keep the item
+// count within 31 bits).  check_every > 0: the residual checks of
+// tpf_run_to_residual run inside the launches (every check_every steps of
+// the call and at its last step); a domain whose residual falls below tol,
+// or that turns non-finite, leaves the queue at that check; each chunk
+// starts from the domains still live.  The entry snapshot is the caller's.
+// Returns TPF_EDEVICE if a wait ever timed out.
+static int run_persistent(tpf_ctx* c, int64_t n, int check_every = 0, double tol = 0.0) {
+    const int nd = (int)c->doms.size();
+    // every domain starts the call live (-1) with its last check at call step 0
+    // (the kernels read both arrays also when no checks run)
+    std::vector<int> minus(nd, -1), zero(nd, 0);
+    HIP_OK(hipMemcpyAsync(c->d_retired, minus.data(), nd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->d_lastchk, zero.data(), nd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
     int64_t done_steps = 0;
     while (done_steps < n) {
-        const int64_t m = std::min<int64_t>(n - done_steps, max_chunk);
-        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_ctl, 2);
-        hipLaunchKernelGGL(zero_ints, dim3((c->doms.size() + 255) / 256), dim3(256), 0, c->stream, c->d_done,
-                           (int)c->doms.size());
+        int rc = refresh_live(c);
+        if (rc) return rc;
+        if (c->live_list.empty()) break;
+        const int ntiles = (int)c->tiles.size(), nlive = (int)c->live_list.size();
+        std::vector<int> per(nd, 0);
+        for (const int4& t : c->tiles) per[t.x]++;
+        HIP_OK(hipMemcpyAsync(c->d_dom_tiles, per.data(), per.size() * sizeof(int), hipMemcpyHostToDevice,
+                              c->stream));
+        HIP_OK(hipMemcpyAsync(c->d_domlist, c->live_list.data(), nlive * sizeof(int), hipMemcpyHostToDevice,
+                              c->stream));
+        bool S = false;  // some live domain has S: the S-capable instance
+        for (const TileGroup& g : c->groups) S = S || g.s;
+        const int code = c->groups[0].code;
+        const int64_t per_step = ntiles + (check_every > 0 ? nlive : 0);
+        int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / per_step);
+        if (check_every > 0) chunk = std::max<int64_t>(check_every, chunk / check_every * check_every);
+        if (chunk * per_step >= ((int64_t)1 << 31)) return TPF_EINVAL;   // a table beyond 2^31 items per chunk
+        const int64_t m = std::min<int64_t>(n - done_steps, chunk);
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_ctl, 3);
+        hipLaunchKernelGGL(zero_ints, dim3((nd + 255) / 256), dim3(256), 0, c->stream, c->d_done, nd);
         HIP_OK(hipGetLastError());
-        hipEvent_t a = nullptr, b = nullptr;
+        HIP_OK(hipMemcpyAsync(c->d_ctl + 2, &nlive, sizeof(int), hipMemcpyHostToDevice, c->stream));
+        hipEvent_t ea = nullptr, eb = nullptr;
         if (c->timing) {
-            HIP_OK(hipEventCreate(&a));
-            HIP_OK(hipEventCreate(&b));
-            HIP_OK(hipEventRecord(a, c->stream));
+            HIP_OK(hipEventCreate(&ea));
+            HIP_OK(hipEventCreate(&eb));
+            HIP_OK(hipEventRecord(ea, c->stream));
         }
-        const PersistentLaunch pl{c->stream, c->d_doms, c->d_tiles, ntiles, (int)m, c->d_dom_tiles,
-                                  c->d_ctl, c->d_done, c->n_cu, 1 << 22};
-        HIP_OK(c->precision == 32 ? launch_persistent_f32(code, S, pl)
-                                  : launch_persistent_f64(code, S, pl));
+        PersistArgs pa{c->d_tiles, ntiles, c->d_domlist, nlive, (int)m, (int)done_steps, (int)n, check_every, tol,
+                       c->d_dom_tiles, c->d_ctl, c->d_done, c->d_retired, c->d_lastchk, c->d_red, 1 << 22};
+        const PersistentLaunch pl{c->stream, c->d_doms, pa, c->n_cu};
+        HIP_OK(c->precision == 32 ? launch_persistent_f32(code, S, pl) : launch_persistent_f64(code, S, pl));
         if (c->timing) {
-            HIP_OK(hipEventRecord(b, c->stream));
-            c->ev_pool.push_back(a);
-            c->ev_pool.push_back(b);
+            HIP_OK(hipEventRecord(eb, c->stream));
+            c->ev_pool.push_back(ea);
+            c->ev_pool.push_back(eb);
             c->ev_steps.push_back(m);
         }
-        int ctl[2] = {0, 0};
+        int ctl[3] = {0, 0, 0};
+        std::vector<int> retired(nd, -1);
+        std::vector<double> stats(4 * nd, 0.0);
         HIP_OK(hipMemcpyAsync(ctl, c->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
+        if (check_every > 0) {
+            HIP_OK(hipMemcpyAsync(retired.data(), c->d_retired, nd * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipMemcpyAsync(stats.data(), c->d_red, 4 * nd * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        }
         HIP_OK(hipStreamSynchronize(c->stream));
         if (ctl[1]) return TPF_EDEVICE;
         for (int di : c->live_list) {
             auto& h = c->doms[di];
-            h.steps += m;
-            h.dev.parity = (int)((h.dev.parity + m) & 1);
+            int64_t took = m;
+            if (check_every > 0) {
+                const int r = retired[di];
+                if (r >= 0) took = r + 1;   // left at the check after its step r of this chunk
+                // the domain's last check within this chunk (call-relative step cs), if any
+                const int64_t first = done_steps + 1, last = done_steps + took;
+                int64_t cs = -1;
+                if (r >= 0 || last == n) cs = last;
+                else if (last / check_every * check_every >= first) cs = last / check_every * check_every;
+                if (cs >= 0) {
+                    h.residual = stats[4 * di + 0];
+                    h.mass = stats[4 * di + 1];
+                    h.snap_step = h.steps + (cs - done_steps);
+                }
+                if (r >= 0) h.status = stats[4 * di + 3] != 0.0 ? TPF_ENAN : 1;
+            }
+            h.steps += took;
+            h.dev.parity = (int)((h.dev.parity + took) & 1);
         }
         int urc = upload_descriptors(c);
         if (urc) return urc;
@@ -724,7 +769,9 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
     c->d_partials = (double*)take(nd * kRedMaxBlocks * 7 * sizeof(double));
     c->d_red = (double*)take(nd * 4 * sizeof(double));
     c->d_scratch = (double*)take(18 * max_nodes(c) * sizeof(double));
-    c->d_ctl = (int*)take(2 * sizeof(int));
+    c->d_ctl = (int*)take(3 * sizeof(int));
+    c->d_retired = (int*)take(nd * sizeof(int));
+    c->d_lastchk = (int*)take(nd * sizeof(int));
     c->d_done = (int*)take(nd * sizeof(int));
     c->d_dom_tiles = (int*)take(nd * sizeof(int));
     if (off > need) return TPF_EINVAL;
@@ -779,7 +826,24 @@ extern "C" int tpf_run_to_residual(tpf_ctx* c, double tol, int32_t check_every, 
     if (rc) return rc;
     int64_t done = 0;
     bool budget = false;
-    while (true) {
+    // launch mode 1 with a tile code that has a persistent form: the checks
+    // run inside the persistent launches and converged domains leave there
+    bool in_launch = false;
+    if (c->launch_mode == 1 && max_steps > 0 && max_steps < (int64_t)1 << 30) {
+        rc = refresh_live(c);
+        if (rc) return rc;
+        in_launch = persistent_ok(c);
+    }
+    if (in_launch) {
+        for (auto& h : c->doms) h.dev.live = stepping(h) ? 1 : 0;
+        rc = upload_descriptors(c);
+        if (rc) return rc;
+        rc = run_persistent(c, max_steps, check_every, tol);
+        if (rc) return rc;
+        for (auto& h : c->doms)
+            if (stepping(h)) budget = true;
+    }
+    while (!in_launch) {
         live.clear();
         for (size_t i = 0; i < c->doms.size(); ++i)
             if (stepping(c->doms[i])) live.push_back((int)i);

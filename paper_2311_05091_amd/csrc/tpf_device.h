@@ -109,6 +109,31 @@ struct DomDev {
     KConst<float> kf;
 };
 
+// Control block and per-domain state of a persistent launch.
+//   ctl[0] next item, ctl[1] failure flag, ctl[2] domains still live.
+//   done[dom]: finished items of dom; retired[dom]: call-relative step at
+//   which dom left (-1 while live); last_check[dom]: call-relative step of
+//   its last residual check; stats[dom][4]: residual, mass, non-finite count,
+//   1 when it left because of non-finite values.
+struct PersistArgs {
+    const int4* tiles;
+    int ntiles;
+    const int* live_doms;   // domains of the tile table, in table order
+    int nlive;
+    int nsteps;             // steps of this launch
+    int step_base;          // steps of the call done by earlier launches
+    int call_steps;         // steps of the whole call (a check also falls on the last)
+    int check_every;        // 0: no residual checks in the launch
+    double tol;
+    const int* dom_tiles;
+    int* ctl;
+    int* done;
+    int* retired;
+    int* last_check;
+    double* stats;
+    int spin_limit;
+};
+
 template <typename T>
 __device__ __forceinline__ const KConst<T>& kconst(const DomDev& d);
 template <>

@@ -12,6 +12,8 @@
 // All global accesses are SoA rows with x fastest, so a wavefront of 64 lanes
 // touches 64 consecutive nodes.
 #pragma once
+#include <type_traits>
+
 #include "tpf_device.h"
 
 namespace tpf {
@@ -601,61 +603,233 @@ __device__ __forceinline__ void strip_body(const DomDev* __restrict__ doms, cons
 }
 
 // ---------------------------------------------------------------------------
-// Persistent launcher: one launch advances every live domain by nsteps steps.
-// Work items (step s, tile t) are handed out in increasing order of
-// s * ntiles + t from a device counter; before working on step s of a
-// domain, a wavefront waits until all tiles of that domain have finished
-// step s - 1 (per-domain completion counter, release/acquire at device
-// scope).  A wave only ever waits for items handed out before its own, and
-// those are held by running waves, so the queue cannot deadlock; a bounded
-// spin sets a failure flag and lets every wave leave should a wait ever
-// exceed the limit.
-//   ctl[0]: next item, ctl[1]: failure flag; done[dom]: finished items of dom;
-//   dom_tiles[dom]: tiles of dom in the table.
-// All control flow in the loop is uniform across the wave: the counters are
-// updated by every lane with an increment of 1 on lane 0 and 0 elsewhere, and
-// values read from memory are broadcast from lane 0 (readfirstlane).  A
-// "lane 0 only" branch at the end and at the start of the loop lets the
-// compiler thread lanes 1..63 past the fetch into a loop of their own that
-// only lane 0 could end: a hang in a one-wave workgroup, whose barrier
-// enforces no reconvergence.
+// FP64 reductions with compensated (Neumaier/TwoSum) accumulation
 // ---------------------------------------------------------------------------
-template <typename T, int CH, bool HAS_S>
-__global__ void __launch_bounds__(64)
-persistent_strip_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int ntiles, int nsteps,
-                        const int* __restrict__ dom_tiles, int* __restrict__ ctl, int* __restrict__ done,
-                        int spin_limit) {
-    __shared__ StripShared<T, HAS_S> sh;
-    const int inc = threadIdx.x == 0 ? 1 : 0;
-    const int total = nsteps * ntiles;
-    for (;;) {
-        const int item = __builtin_amdgcn_readfirstlane(atomicAdd(&ctl[0], inc));
-        if (item >= total) break;
-        const int s = item / ntiles, t = item - s * ntiles;
-        const int4 tile = tiles[t];
-        if (s > 0) {
-            const int need = s * dom_tiles[tile.x];
-            int it = 0;
-            bool fail = false;
-            while (__builtin_amdgcn_readfirstlane(
-                       __hip_atomic_load(&done[tile.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) < need) {
-                if (++it > spin_limit ||
-                    __builtin_amdgcn_readfirstlane(
-                        __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
-                    fail = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+struct CSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void csum_add(CSum& a, double v) {
+    double t = a.s + v;
+    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+    else a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void csum_merge(CSum& a, const CSum& b) {
+    csum_add(a, b.s);
+    a.c += b.c;
+}
+
+// Residual check of one domain inside the launch, by one workgroup: phi1 of
+// the state after call step `cs` (pulled sums of the CH populations in
+// buffer `buf`), sum (phi1 - snap)^2, sum phi1^2, sum phi1 and the
+// non-finite count in FP64 (compensated per thread, then a fixed-order tree),
+// snap <- phi1; the residual as in tpf_run_to_residual.  Returns the
+// decision, the same in every thread: 0 live, 1 converged, 2 non-finite.
+template <typename T, int NW>
+__device__ int persist_check(const DomDev& d, int dom, int buf, int cs, double tol, int* __restrict__ last_check,
+                             double* __restrict__ stats, double* red) {
+    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    gptr<const T> fin = gpc<T>(d.f[buf]);
+    gptr<double> snap = gp<double>(d.snap);
+    CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
+    double bad = 0.0;
+    for (int id = threadIdx.x; id < N; id += 64 * NW) {
+        const int y = id / nx, x = id - y * nx;
+        T sum = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) sum += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
+        const double v = double(sum);
+        if (!isfinite(v)) bad += 1.0;
+        csum_add(m, v);
+        csum_add(n2, v * v);
+        const double prev = snap[id];
+        if (isfinite(prev)) csum_add(r, (v - prev) * (v - prev));
+        snap[id] = v;
+    }
+    // fixed-order tree over the workgroup in LDS
+    double* sh = red;  // [7][64 NW]
+    const int T_ = 64 * NW;
+    sh[0 * T_ + threadIdx.x] = m.s; sh[1 * T_ + threadIdx.x] = m.c;
+    sh[2 * T_ + threadIdx.x] = r.s; sh[3 * T_ + threadIdx.x] = r.c;
+    sh[4 * T_ + threadIdx.x] = n2.s; sh[5 * T_ + threadIdx.x] = n2.c;
+    sh[6 * T_ + threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = T_ / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            for (int j = 0; j < 3; ++j) {
+                CSum x = {sh[2 * j * T_ + threadIdx.x], sh[(2 * j + 1) * T_ + threadIdx.x]};
+                csum_merge(x, CSum{sh[2 * j * T_ + o], sh[(2 * j + 1) * T_ + o]});
+                sh[2 * j * T_ + threadIdx.x] = x.s;
+                sh[(2 * j + 1) * T_ + threadIdx.x] = x.c;
             }
-            if (fail) {
-                __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
+            sh[6 * T_ + threadIdx.x] += sh[6 * T_ + o];
+        }
+        __syncthreads();
+    }
+    const double mass = sh[0] + sh[T_], d2 = sh[2 * T_] + sh[3 * T_], nn = sh[4 * T_] + sh[5 * T_];
+    const double nbad = sh[6 * T_];
+    const int prev_check = last_check[dom];
+    const double res = (nn > 0.0 && cs > prev_check) ? sqrt(d2) / ((double)(cs - prev_check) * sqrt(nn)) : NAN;
+    __syncthreads();   // every thread has read the tree before the next item reuses it
+    const int verdict = (nbad > 0.0 || !isfinite(mass)) ? 2 : ((isfinite(res) && res < tol) ? 1 : 0);
+    if (threadIdx.x < 64) {   // wavefront 0, every lane the same values
+        last_check[dom] = cs;
+        stats[4 * dom + 0] = res;
+        stats[4 * dom + 1] = mass;
+        stats[4 * dom + 2] = nbad;
+        stats[4 * dom + 3] = verdict == 2 ? 1.0 : 0.0;
+    }
+    return verdict;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent launcher: one launch advances every live domain by a.nsteps
+// steps.  Work items are handed out in increasing order from a device
+// counter.  Without residual checks step s holds the ntiles tile items of
+// the table.  With checks every K = check_every steps, the items come in
+// blocks of K steps: the K ntiles tile items (step by step), then one check
+// item per live domain for the block's last step; the launch's last block
+// may be shorter (the call's last step, which also gets a check).
+// Before step s of a domain a workgroup waits until the domain's tiles of
+// steps < s and its checks of earlier blocks have finished; a check item
+// waits for the tiles of its own step (per-domain completion counters,
+// release/acquire at device scope).  A workgroup only ever waits for items
+// handed out before its own, held by running workgroups, so the queue cannot
+// deadlock; a bounded spin sets a failure flag and lets every workgroup
+// leave should a wait exceed the limit.  A domain whose check finds
+// r < tol, or non-finite values, leaves: its later items are no-ops, and
+// when no domain is left every workgroup leaves.
+//   NW = 1: single strips (tile codes 8-10); NW > 1: lockstep groups of NW
+//   strips (codes 17-24), as in strip_group_body.
+// All control flow in the loop is uniform within each wavefront, and every
+// wavefront meets the same barriers: wavefront 0 fetches, waits and
+// decides, and broadcasts through LDS; the others take an acquire fence
+// after the barrier that ends the wait.  (A "lane 0 only" branch around the
+// item fetch once let lanes 1..63 of a one-wave workgroup run ahead into a
+// loop of their own: a hang.)
+// ---------------------------------------------------------------------------
+template <typename T, int CH, bool HAS_S, int NW, int NT, bool SHARE>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NW > 1 ? 3 : 1, 8)))
+persistent_kernel(const DomDev* __restrict__ doms, PersistArgs a) {
+    constexpr bool GROUP = NW > 1;
+    using Shared = typename std::conditional<GROUP && SHARE, GroupShared<T, HAS_S, NW>,
+                                             StripShared<T, HAS_S>>::type;
+    __shared__ Shared rings[(GROUP && !SHARE) ? NW : 1];
+    __shared__ double red[7 * 64 * NW];
+    __shared__ int bc[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool checks = a.check_every > 0;
+    const int K = checks ? a.check_every : a.nsteps;            // steps per block
+    const int block_items = K * a.ntiles + (checks ? a.nlive : 0);
+    const int full = a.nsteps / K, rem = a.nsteps - full * K;
+    const int total = full * block_items + rem * a.ntiles + (checks && rem > 0 ? a.nlive : 0);
+    for (;;) {
+        // ---- fetch (wavefront 0) and broadcast ----
+        if (w == 0) {
+            const int item = __builtin_amdgcn_readfirstlane(atomicAdd(&a.ctl[0], lane == 0 ? 1 : 0));
+            const int live = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            bc[0] = item;
+            bc[1] = live;
+        }
+        __syncthreads();
+        const int item = bc[0], live_now = bc[1];
+        __syncthreads();
+        if (item >= total || live_now <= 0) break;
+        const int b = item / block_items, r = item - b * block_items;
+        const int steps_b = b < full ? K : rem;
+        const bool is_check = r >= steps_b * a.ntiles;
+        const int s = b * K + (is_check ? steps_b - 1 : r / a.ntiles);
+        const int k = is_check ? r - steps_b * a.ntiles : r - (r / a.ntiles) * a.ntiles;
+        const int dom = is_check ? a.live_doms[k] : a.tiles[k].x;
+        const int tiles_d = a.dom_tiles[dom];
+        // finished items of dom this item needs: tiles of steps < s (< s + 1
+        // for a check) and the checks of earlier blocks
+        const int need = tiles_d * (is_check ? s + 1 : s) + (checks ? s / K : 0);
+        // ---- wait (wavefront 0) and vote ----
+        if (w == 0) {
+            int verdict = 0;   // 0 go on, 1 failure, 2 no domain left
+            if (need > 0) {
+                // relaxed polls (an acquire per poll would invalidate the
+                // caches each time), one acquire fence once the count is met;
+                // the live count and the failure flag every 32nd poll
+                int it = 0;
+                for (;;) {
+                    const int got = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&a.done[dom], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (got >= need) break;
+                    ++it;
+                    if ((it & 31) == 0) {
+                        if (__builtin_amdgcn_readfirstlane(
+                                __hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= 0) {
+                            verdict = 2;
+                            break;
+                        }
+                        if (it > a.spin_limit || __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                                     &a.ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
+                            verdict = 1;
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (verdict == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            bc[2] = verdict;
+        }
+        __syncthreads();
+        const int vote = bc[2];
+        __syncthreads();
+        if (vote == 1) {
+            if (w == 0) __hip_atomic_store(&a.ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        if (vote == 2) break;
+        // the other wavefronts read what the awaited items wrote after the
+        // barrier that follows wavefront 0's acquire (one compute unit, one
+        // vector L1, invalidated by that acquire)
+        const DomDev& d = doms[dom];
+        const int rstep = a.retired[dom];
+        const bool active = rstep < 0;   // a check of step s - 1 has been seen (acquire above)
+        if (active) {
+            if (is_check) {
+                const int cs = a.step_base + s + 1;
+                const int buf = (d.parity + s + 1) & 1;
+                const int verdict = persist_check<T, NW>(d, dom, buf, cs, a.tol, a.last_check, a.stats, red);
+                if (verdict != 0 && w == 0) {   // wavefront 0 as a whole
+                    a.retired[dom] = s;
+                    __hip_atomic_fetch_add(&a.ctl[2], lane == 0 ? -1 : 0, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else {
+                const int4 tile = a.tiles[k];
+                if constexpr (!GROUP) {
+                    strip_tile<T, CH, HAS_S, kModeStep, NT>(d, rings[0], tile.y, tile.z, s, nullptr);
+                } else {
+                    const int x0 = tile.y + 64 * w;
+                    if (x0 >= d.nx) {
+                        for (int r = 0; r < CH + 4; ++r) {
+                            __syncthreads();
+                            __syncthreads();
+                        }
+                    } else if constexpr (SHARE) {
+                        const GroupRing<T, HAS_S, NW> ring{rings[0], 64 * w, w == 0, w == NW - 1 || x0 + 64 >= d.nx};
+                        strip_tile_r<T, CH, HAS_S, kModeStep, NT>(d, ring, x0, tile.z, s, nullptr);
+                    } else {
+                        strip_tile<T, CH, HAS_S, kModeStep, NT>(d, rings[w], x0, tile.z, s, nullptr);
+                    }
+                }
             }
         }
-        const DomDev& d = doms[tile.x];
-        strip_tile<T, CH, HAS_S, kModeStep>(d, sh, tile.y, tile.z, s, nullptr);
+        // every wavefront waits until its own stores have reached the L2
+        // before wavefront 0's release (which writes the L2 back for the
+        // other XCDs) publishes the item
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        __hip_atomic_fetch_add(&done[tile.x], inc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0) __hip_atomic_fetch_add(&a.done[dom], lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -779,25 +953,6 @@ __global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const doub
         gp<T>(d.psi[1])[id] = T(0);
     }
     gp<double>(d.snap)[id] = __builtin_nan("");
-}
-
-// ---------------------------------------------------------------------------
-// FP64 reductions with compensated (Neumaier/TwoSum) accumulation
-// ---------------------------------------------------------------------------
-struct CSum {
-    double s, c;
-};
-
-__device__ __forceinline__ void csum_add(CSum& a, double v) {
-    double t = a.s + v;
-    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
-    else a.c += (v - t) + a.s;
-    a.s = t;
-}
-
-__device__ __forceinline__ void csum_merge(CSum& a, const CSum& b) {
-    csum_add(a, b.s);
-    a.c += b.c;
 }
 
 constexpr int kRedMaxBlocks = 256;  // partial-sum blocks per domain (upper bound)

@@ -19,24 +19,20 @@ struct TileLaunch {
     double* mom;   // moments output (mode 1), else null
 };
 
-// One persistent launch: nsteps steps of every domain in the tile table.
+// One persistent launch: a.nsteps steps of every domain in the tile table,
+// with residual checks when a.check_every > 0.
 struct PersistentLaunch {
     hipStream_t stream;
     const DomDev* doms;
-    const int4* tiles;
-    int ntiles;
-    int nsteps;
-    const int* dom_tiles;
-    int* ctl;
-    int* done;
+    PersistArgs a;
     int n_cu;
-    int spin_limit;
 };
 
 // hipErrorInvalidValue for an unknown tile code.
 hipError_t launch_tiles_f32(int code, bool with_s, int mode, const TileLaunch& a);
 hipError_t launch_tiles_f64(int code, bool with_s, int mode, const TileLaunch& a);
-// Strip codes 8-10 only.
+// Strip codes 8-10 and group codes 17, 20-24.
+bool persistent_code(int code);
 hipError_t launch_persistent_f32(int code, bool with_s, const PersistentLaunch& a);
 hipError_t launch_persistent_f64(int code, bool with_s, const PersistentLaunch& a);
 

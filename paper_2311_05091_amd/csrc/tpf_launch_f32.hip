@@ -8,4 +8,7 @@ hipError_t launch_tiles_f32(int code, bool with_s, int mode, const TileLaunch& a
 hipError_t launch_persistent_f32(int code, bool with_s, const PersistentLaunch& a) {
     return launch_persistent<float>(code, with_s, a);
 }
+bool persistent_code(int code) {
+    return code == 8 || code == 9 || code == 10 || code == 17 || (code >= 20 && code <= 24);
+}
 }  // namespace tpf

@@ -64,28 +64,42 @@ hipError_t launch_tiles(int code, bool with_s, int mode, const TileLaunch& a) {
 }
 
 // Persistent launch: a grid of the device's resident capacity (occupancy x
-// compute units), capped at the number of work items.
-template <typename T, int CH, bool S>
-hipError_t launch_persistent_t(const PersistentLaunch& a) {
+// compute units), capped at twice the items of one step (more workgroups
+// would only wait on later steps) and at the number of work items.
+template <typename T, int CH, bool S, int NW, int NT, bool SHARE>
+hipError_t launch_persistent_t(const PersistentLaunch& p) {
+    auto k = persistent_kernel<T, CH, S, NW, NT, SHARE>;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_strip_kernel<T, CH, S>, 64, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * NW, 0);
     if (e != hipSuccess) return e;
     if (per_cu <= 0) per_cu = 1;
-    const int64_t total = (int64_t)a.nsteps * a.ntiles;
-    const int grid = (int)std::min<int64_t>((int64_t)per_cu * a.n_cu, total);
-    hipLaunchKernelGGL((persistent_strip_kernel<T, CH, S>), dim3(grid), dim3(64), 0, a.stream, a.doms, a.tiles,
-                       a.ntiles, a.nsteps, a.dom_tiles, a.ctl, a.done, a.spin_limit);
+    const int64_t per_step = p.a.ntiles + (p.a.check_every > 0 ? p.a.nlive : 0);
+    const int64_t total = (int64_t)p.a.nsteps * per_step;
+    const int64_t cap = std::min<int64_t>((int64_t)per_cu * p.n_cu, 2 * per_step);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cap, total));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * NW), 0, p.stream, p.doms, p.a);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_persistent(int code, bool with_s, const PersistentLaunch& a) {
+template <typename T, bool S>
+hipError_t launch_persistent_s(int code, const PersistentLaunch& p) {
     switch (code) {
-        case 8: return with_s ? launch_persistent_t<T, 16, true>(a) : launch_persistent_t<T, 16, false>(a);
-        case 9: return with_s ? launch_persistent_t<T, 32, true>(a) : launch_persistent_t<T, 32, false>(a);
-        case 10: return with_s ? launch_persistent_t<T, 64, true>(a) : launch_persistent_t<T, 64, false>(a);
+        case 8: return launch_persistent_t<T, 16, S, 1, 0, false>(p);
+        case 9: return launch_persistent_t<T, 32, S, 1, 0, false>(p);
+        case 10: return launch_persistent_t<T, 64, S, 1, 0, false>(p);
+        case 17:
+        case 21: return launch_persistent_t<T, 32, S, 4, 0, true>(p);
+        case 20: return launch_persistent_t<T, 16, S, 4, 0, true>(p);
+        case 22: return launch_persistent_t<T, 64, S, 4, 0, true>(p);
+        case 23: return launch_persistent_t<T, 64, S, 4, 3, false>(p);
+        case 24: return launch_persistent_t<T, 64, S, 4, 1, true>(p);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_persistent(int code, bool with_s, const PersistentLaunch& p) {
+    return with_s ? launch_persistent_s<T, true>(code, p) : launch_persistent_s<T, false>(code, p);
 }
 
 }  // namespace tpf

@@ -311,7 +311,8 @@ class Context:
         _check(self.lib.tpf_set_tile(self._h, int(code)), "tpf_set_tile")
 
     def set_launch_mode(self, mode: int):
-        """0: one launch per step; 1: one persistent launch per call (strip tiles);
+        """0: one launch per step; 1: persistent launches (strip and strip-group
+        tiles; the residual checks of run_to_residual run inside them);
         2: one launch per step, tile shape chosen from the live work."""
         _check(self.lib.tpf_set_launch_mode(self._h, int(mode)), "tpf_set_launch_mode")
 

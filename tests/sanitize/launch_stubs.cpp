@@ -9,6 +9,7 @@ hipError_t launch_tiles_f32(int, bool, int, const TileLaunch&) { return hipError
 hipError_t launch_tiles_f64(int, bool, int, const TileLaunch&) { return hipErrorInvalidValue; }
 hipError_t launch_persistent_f32(int, bool, const PersistentLaunch&) { return hipErrorInvalidValue; }
 hipError_t launch_persistent_f64(int, bool, const PersistentLaunch&) { return hipErrorInvalidValue; }
+bool persistent_code(int) { return false; }
 }  // namespace tpf
 
 namespace tpf3 {

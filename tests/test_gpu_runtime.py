@@ -6,6 +6,7 @@ import math
 import os
 import sys
 import tempfile
+import time
 
 import numpy as np
 import pytest
@@ -432,6 +433,92 @@ def test_persistent_launch_matches_per_step_launch(prec, tile):
     assert rc == lbm.TPF_EBUDGET and (steps == 100).all()
     a.close()
     b.close()
+
+
+def _converging_batch():
+    return [
+        G.flat_wall_droplet(nx=64, ny=32, wall_rows=5, R0=10, theta_deg=60.0),
+        G.flat_wall_droplet(nx=96, ny=40, wall_rows=6, R0=12, theta_deg=90.0),
+        G.flat_wall_droplet(nx=150, ny=45, wall_rows=5, R0=12, theta_deg=120.0),
+    ]
+
+
+@pytest.mark.parametrize("prec,tile", [(64, 9), (64, 21), (64, 23), (32, 9), (32, 21), (32, 23)])
+def test_persistent_run_to_residual_retires_inside_the_launch(prec, tile):
+    """Launch mode 1 runs the residual checks of run_to_residual inside the
+    persistent launch (one check item per live domain and step, active at
+    every check_every-th step of the call and at its last step); a domain
+    whose residual falls below tol leaves the work queue there while the
+    others go on.  Against one launch per step with checks on the host: the
+    same retirement steps (FP64; FP32 within one check interval, since the
+    two kernels round differently), the same residual (FP64 to 1e-8
+    relative), the same state (FP64 1e-13; FP32 1e-5 of the largest
+    population where the steps agree), and the budget case ends at
+    max_steps with the final check taken at that step."""
+    specs = _converging_batch()
+    _say("persistent residual", prec, tile)
+    tol, every = 1e-5, 100
+    a = gpu_context(specs, precision=prec, tile=tile)
+    t0 = time.perf_counter()
+    rc_a, st_a = a.run_to_residual(tol, check_every=every, max_steps=100000)
+    t1 = time.perf_counter()
+    b = gpu_context(specs, precision=prec, tile=tile)
+    b.set_launch_mode(1)
+    rc_b, st_b = b.run_to_residual(tol, check_every=every, max_steps=100000)
+    t2 = time.perf_counter()
+    print("steps per domain %s (per-step launches, %.2f s) %s (persistent, %.2f s)"
+          % (st_a.tolist(), t1 - t0, st_b.tolist(), t2 - t1), flush=True)
+    assert rc_a == lbm.TPF_OK and rc_b == lbm.TPF_OK
+    assert len(set(st_a.tolist())) > 1, st_a      # the domains leave at different steps
+    if prec == 64:
+        assert (st_a == st_b).all(), (st_a, st_b)
+    else:
+        assert np.abs(st_a - st_b).max() <= every, (st_a, st_b)
+    ptol = 1e-13 if prec == 64 else 1e-5
+    for i in range(len(specs)):
+        da, db = a.diag(i), b.diag(i)
+        assert db["status"] == lbm.TPF_OK and db["steps"] == st_b[i] and st_b[i] % every == 0
+        assert db["residual"] < tol and da["residual"] < tol
+        if st_a[i] == st_b[i]:
+            if prec == 64:
+                assert abs(db["residual"] / da["residual"] - 1) < 1e-8, (da, db)
+                assert abs(db["mass"] / da["mass"] - 1) < 1e-13
+            fa, ga = a.populations(i)
+            fb, gb = b.populations(i)
+            assert np.abs(fa - fb).max() <= ptol * np.abs(fa).max()
+            assert np.abs(ga - gb).max() <= ptol * max(np.abs(ga).max(), 1e-12)
+    # budget: no domain converges; the last check falls on max_steps = 130
+    # (not a multiple of check_every), and later calls step every domain again
+    for c in (a, b):
+        rc, st = c.run_to_residual(1e-30, check_every=50, max_steps=130)
+        assert rc == lbm.TPF_EBUDGET and (st == 130).all()
+    for i in range(len(specs)):
+        da, db = a.diag(i), b.diag(i)
+        assert da["steps"] == st_a[i] + 130 and db["steps"] == st_b[i] + 130
+        if st_a[i] == st_b[i] and prec == 64:
+            assert abs(db["residual"] / da["residual"] - 1) < 1e-8, (i, da, db)
+    a.close()
+    b.close()
+
+
+def test_persistent_run_to_residual_isolates_a_nan_domain():
+    """In launch mode 1 a domain that turns non-finite leaves at its first
+    check with TPF_ENAN while the others run to max_steps, as in mode 0."""
+    specs = _mixed_batch()[:2]
+    bad = G.with_params(specs[0], phi1=specs[0].phi1.copy())
+    bad.phi1[5, 7] = 2.0e3     # finite at entry, non-finite within a few steps
+    _say("persistent nan isolation")
+    out = []
+    for mode in (0, 1):
+        ctx = gpu_context([bad, specs[1]], precision=32, tile=9)
+        ctx.set_launch_mode(mode)
+        rc, steps = ctx.run_to_residual(1e-30, check_every=50, max_steps=200)
+        out.append((rc, steps.tolist(), ctx.diag(0)["status"], ctx.diag(1)["status"]))
+        ctx.close()
+    assert out[0] == out[1], out
+    rc, steps, s0, s1 = out[1]
+    assert rc == lbm.TPF_ENAN and s0 == lbm.TPF_ENAN and s1 == lbm.TPF_OK
+    assert steps[1] == 200 and steps[0] < 200
 
 
 @pytest.mark.parametrize("prec", [64, 32])
