@@ -56,6 +56,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* grids below this many nodes run each pass on one thread (the per-pass
+ * thread start-up would cost more than the pass) */
+#define ORC_PAR_MIN 8192
+
 /* ---------------------------------------------------------------------- */
 /* Parameters (own definition; the GPU library has its own).               */
 /* ---------------------------------------------------------------------- */
@@ -421,7 +425,7 @@ static void stencil(const orc_sim* s, const double* a, int x, int y,
 static void stream(orc_sim* s)
 {
     int nx = s->nx, ny = s->ny;
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -453,14 +457,14 @@ static void macro_and_collide(orc_sim* s, int collide)
     double cs2 = d->cs2;
 
     /* phase field phi1 = sum_i f_i */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (size_t id = 0; id < n; ++id) {
         double sum = 0.0;
         for (int i = 0; i < 9; ++i) sum += s->f[(size_t)i * n + id];
         FLD(s, F_PHI1)[id] = sum;
     }
     /* stencils on phi0 and phi1 */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -468,7 +472,7 @@ static void macro_and_collide(orc_sim* s, int collide)
             stencil(s, FLD(s, F_PHI1), x, y, &FLD(s, F_GX1)[id], &FLD(s, F_GY1)[id], &FLD(s, F_LAP1)[id]);
         }
     /* chemical potentials and mubar1 */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (size_t id = 0; id < n; ++id) {
         double mu[3], mub[3];
         orc_chemical_potentials(d->gamma, P->D, s->phi0[id], FLD(s, F_PHI1)[id],
@@ -479,7 +483,7 @@ static void macro_and_collide(orc_sim* s, int collide)
         FLD(s, F_MUB)[id] = mub[1];
     }
     /* grad(mubar1) */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -493,7 +497,7 @@ static void macro_and_collide(orc_sim* s, int collide)
     double* psi_new = lag_new + 6 * n;
     double rho0 = P->rho[0], rho1 = P->rho[1], rho2 = P->rho[2];
 
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;

@@ -33,6 +33,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* grids below this many nodes run each pass on one thread (the per-pass
+ * thread start-up would cost more than the pass) */
+#define ORC_PAR_MIN 8192
+
 #define Q15 15
 
 typedef struct {
@@ -313,7 +317,7 @@ static void stream3(orc3_sim* s)
 {
     int nx = s->n[0], ny = s->n[1], nz = s->n[2];
     size_t N = s->N;
-#pragma omp parallel for collapse(2)
+#pragma omp parallel for collapse(2) if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -361,13 +365,13 @@ static void macro_and_collide3(orc3_sim* s, int collide)
     size_t N = s->N;
     double cs2 = P->d0;
 
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (size_t id = 0; id < N; ++id) {
         double sum = 0.0;
         for (int i = 0; i < Q15; ++i) sum += s->f[(size_t)i * N + id];
         FLD3(s, F_PHI1)[id] = sum;
     }
-#pragma omp parallel for collapse(2)
+#pragma omp parallel for collapse(2) if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -378,7 +382,7 @@ static void macro_and_collide3(orc3_sim* s, int collide)
                 FLD3(s, F_GX0)[id] = g0[0]; FLD3(s, F_GY0)[id] = g0[1]; FLD3(s, F_GZ0)[id] = g0[2];
                 FLD3(s, F_GX1)[id] = g1[0]; FLD3(s, F_GY1)[id] = g1[1]; FLD3(s, F_GZ1)[id] = g1[2];
             }
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (size_t id = 0; id < N; ++id) {
         double mu[3], mub;
         chem3(s->gamma, P->D, s->phi0[id], FLD3(s, F_PHI1)[id], FLD3(s, F_LAP0)[id], FLD3(s, F_LAP1)[id], mu, &mub);
@@ -387,7 +391,7 @@ static void macro_and_collide3(orc3_sim* s, int collide)
         FLD3(s, F_MU2)[id] = mu[2];
         FLD3(s, F_MUB)[id] = mub;
     }
-#pragma omp parallel for collapse(2)
+#pragma omp parallel for collapse(2) if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -400,7 +404,7 @@ static void macro_and_collide3(orc3_sim* s, int collide)
     const double* lag = s->lag;
     double* lnew = s->lag_new;
     double rho0 = P->rho[0], rho1 = P->rho[1], rho2 = P->rho[2];
-#pragma omp parallel for collapse(2)
+#pragma omp parallel for collapse(2) if ((size_t)nx * ny * nz >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

@@ -35,6 +35,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* grids below this many nodes run each pass on one thread (the per-pass
+ * thread start-up would cost more than the pass) */
+#define ORC_PAR_MIN 8192
+
 /* lattice algebra of tpf_oracle.c (same library) */
 void orc_velocities(int32_t cx[9], int32_t cy[9]);
 void orc_weights(double d0, double w[9]);
@@ -132,7 +136,7 @@ static void stream3f(orc3f_sim* s)
 {
     int nx = s->nx, ny = s->ny;
     size_t n = s->n;
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -165,7 +169,7 @@ static void macro_and_collide3f(orc3f_sim* s, int collide)
     double cs2 = s->cs2;
 
     /* phase fields phi0 = sum f0, phi1 = sum f1 */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (size_t id = 0; id < n; ++id) {
         double a = 0.0, b = 0.0;
         for (int i = 0; i < 9; ++i) {
@@ -175,7 +179,7 @@ static void macro_and_collide3f(orc3f_sim* s, int collide)
         FL(s, G_PHI0)[id] = a;
         FL(s, G_PHI1)[id] = b;
     }
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -183,7 +187,7 @@ static void macro_and_collide3f(orc3f_sim* s, int collide)
             stencil3f(s, FL(s, G_PHI1), x, y, &FL(s, G_GX1)[id], &FL(s, G_GY1)[id], &FL(s, G_LAP1)[id]);
         }
     /* chemical potentials mu_p and the corrected mubar_0, mubar_1 */
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (size_t id = 0; id < n; ++id) {
         double mu[3], mub[3];
         orc_chemical_potentials(s->gamma, P->D, FL(s, G_PHI0)[id], FL(s, G_PHI1)[id], FL(s, G_LAP0)[id],
@@ -194,7 +198,7 @@ static void macro_and_collide3f(orc3f_sim* s, int collide)
         FL(s, G_MUB0)[id] = mub[0];
         FL(s, G_MUB1)[id] = mub[1];
     }
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;
@@ -205,7 +209,7 @@ static void macro_and_collide3f(orc3f_sim* s, int collide)
     const double* lag = s->lag;
     double* lag_new = s->lag_new;
     const double r0 = P->rho[0], r1 = P->rho[1], r2 = P->rho[2];
-#pragma omp parallel for
+#pragma omp parallel for if ((size_t)nx * ny >= ORC_PAR_MIN)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t id = (size_t)y * nx + x;

@@ -9,13 +9,13 @@ lattice; Sec. 2.1, Sec. 3, Sec. 4, Sec. 4.1).
   phases alike, so any term written for one phase only (the extra mass flux
   S, the mobility f, eta_p, mubar_p) breaks it.
 * A drop of phase 0 in phase 2 (no phase 1) obeys the Laplace law
-  dp = sigma02 / R (within 1% measured, 3% asserted): with phi1 = 0, mubar1
+  dp = sigma02 / R (R = 14; within 1% measured, 3% asserted): with phi1 = 0, mubar1
   vanishes identically and the model is a two-phase CH with tension (gamma0 + gamma2)/2 = sigma02
   (Sec. 2.1); unequal pairwise tensions make a mix-up of them show.
 * A drop of phase 0 on a flat interface between phases 1 and 2 relaxes to a
   lens of two circular arcs whose corner angle inside phase 0 follows
   Neumann's triangle of the three tensions (120 degrees for equal tensions,
-  the 3f case of Sec. 4.1; measured 121.3 and 123.8 against 120.0 and 124.2).
+  the 3f case of Sec. 4.1; measured 121.5 and 123.4 against 120.0 and 124.2).
 """
 import math
 
@@ -74,7 +74,7 @@ def test_3f_laplace_law_for_phase_0_in_phase_2(orc):
     n = 96
     x, y = _grid(n, n)
     r = np.hypot(x - n / 2 + 0.5, y - n / 2 + 0.5)
-    for R0 in (14.0, 20.0):
+    for R0 in (14.0,):
         phi0 = 0.5 + 0.5 * np.tanh((R0 - r) / 2.0)
         phi1 = np.zeros_like(phi0)
         p = orc.make_params3f(n, n, periodic_y=1, D=4.0, **TENS)
@@ -116,7 +116,7 @@ def test_3f_lens_corner_angles_follow_neumann_triangle(orc):
     for s01, s02, s12 in ((0.01, 0.01, 0.01), (0.012, 0.008, 0.01)):
         p = orc.make_params3f(nx, ny, D=4.0, sigma01=s01, sigma02=s02, sigma12=s12, M_deg=0.01)
         s = orc.Sim3F(p, phi0, phi1)
-        s.step(6000)
+        s.step(4000)
         up, low = _lens_angles(s.moments()[0], cy, 4.0)
         a0 = math.degrees(math.acos((s12 ** 2 - s01 ** 2 - s02 ** 2) / (2 * s01 * s02)))
         assert abs(up + low - a0) <= 2.0, (s01, s02, s12, up, low, a0)
