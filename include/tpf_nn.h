@@ -35,7 +35,10 @@ int tpfnn_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, void* st
 
 /* y[n,h,w,co] = act(bias[co] + sum_{ky,kx,ci} w[co,ky,kx,ci] x[n,h+ky-1,w+kx-1,ci]),
  * zero padding, act = ReLU when relu != 0.  bias may be NULL.  Cin, Cout
- * multiples of 32. */
+ * multiples of 32, H W a multiple of 64.  Layers with Cout a multiple of 64
+ * and W a multiple of 128 (or W = 16, 32, 64 with H holding 128 / W rows)
+ * run a kernel that stages each 32-channel input patch and the weights of
+ * all nine taps in LDS once per chunk; the others stage one tap at a time. */
 int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_t W, int32_t Cin,
                       const uint16_t* w, const float* bias, int32_t Cout, int32_t relu,
                       uint16_t* y, void* stream);

@@ -133,6 +133,178 @@ conv3x3_fwd_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint1
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution, forward, for wide layers (Cout a multiple of 128, Cin of
+// 32).  A block computes BM pixels x 128 output channels with 2 x 2
+// wavefronts of (BM / 2) x 64 outputs each (BM / 32 x 4 MFMA tiles of
+// 16 x 16).  The K loop runs over 9 taps x Cin / 32 channel chunks; each step
+// stages 32 channels of BM pixels and of 128 output channels in one of two
+// LDS buffers: the next step's global loads are issued before the current
+// step's MFMAs and stored into the other buffer after them, so a step needs
+// one barrier.
+// ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// 3x3 convolution, forward, staging input patches (Cout a multiple of 64, Cin
+// of 32; W a multiple of 128 or a divisor of 128 of at least 16).  A block
+// of 2 PXB threads computes PXB output pixels (R = PXB / WB image rows of
+// WB = min(W, 128) columns) x 64 output channels; its PXB / 64 x 2
+// wavefronts compute 64 x 32 outputs each.  For each chunk of 32 input
+// channels it stages in LDS the input patch of those pixels (R + 2 rows of
+// WB + 2 columns, zero outside the image) and the 64 x 9 weights, and then
+// runs all nine taps on them: each tap's A operand is the patch shifted by
+// (ky, kx).  The next chunk's global loads are in flight (in registers) while
+// the current chunk is computed; a chunk costs two barriers.
+// ---------------------------------------------------------------------------
+constexpr int kPatchCo = 64;
+constexpr int kPatchKP = 40;   // LDS row pitch in halfwords (32 channels + padding): the 16 rows of an operand in distinct banks
+
+template <int WB, int PXB>
+struct PatchCfg {
+    static constexpr int NTH = 2 * PXB;                  // threads per block
+    static constexpr int R = PXB / WB;                   // image rows per block
+    static constexpr int PC = WB + 2;                    // patch columns
+    static constexpr int PIX = (R + 2) * PC;             // patch pixels
+    static constexpr int PL = (PIX * 4 + NTH - 1) / NTH;             // 16-byte patch loads per thread
+    static constexpr int WROWS = kPatchCo * 9;                        // (tap, co) weight rows
+    static constexpr int WL = (WROWS * 4 + NTH - 1) / NTH;           // 16-byte weight loads per thread
+};
+
+// One input-channel chunk of the patch kernel in registers: PL patch pixels
+// and WL weight rows of 16 bytes per thread.
+template <int PL, int WL>
+struct PatchRegs {
+    uint4 p[PL];
+    uint4 w[WL];
+};
+
+// Global loads of the chunk ci0 .. ci0 + 31 (patch pixels read as zero where
+// pval is false).  Weight row i = (tap, co) with co fastest, so that the LDS
+// store spreads consecutive rows over distinct banks; rows past the last
+// (when the thread count does not divide them) read row 0 and are not stored.
+template <typename C>
+__device__ __forceinline__ PatchRegs<C::PL, C::WL> patch_load(const uint16_t* __restrict__ x,
+                                                              const uint16_t* __restrict__ w, int Cin, int co0, int tid,
+                                                              int seg, const int (&poff)[C::PL],
+                                                              const bool (&pval)[C::PL], int ci0) {
+    PatchRegs<C::PL, C::WL> g;
+#pragma unroll
+    for (int k = 0; k < C::PL; ++k) {
+        const uint4 v = *(const uint4*)(x + (size_t)poff[k] * Cin + ci0 + seg);
+        g.p[k] = pval[k] ? v : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < C::WL; ++k) {
+        int i = (tid + C::NTH * k) >> 2;
+        if (i >= C::WROWS) i = 0;
+        const int kk = i / kPatchCo, co = i - kk * kPatchCo;
+        g.w[k] = *(const uint4*)(w + ((size_t)(co0 + co) * 9 + kk) * Cin + ci0 + seg);
+    }
+    return g;
+}
+
+template <typename C>
+__device__ __forceinline__ void patch_store(uint16_t (*Ps)[kPatchKP], uint16_t (*Ws)[kPatchCo][kPatchKP], int tid,
+                                            int seg, const PatchRegs<C::PL, C::WL>& g) {
+#pragma unroll
+    for (int k = 0; k < C::PL; ++k) {
+        const int i = (tid + C::NTH * k) >> 2;
+        if (i < C::PIX) *(uint4*)&Ps[i][seg] = g.p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < C::WL; ++k) {
+        const int i = (tid + C::NTH * k) >> 2;
+        const int kk = i / kPatchCo, co = i - kk * kPatchCo;
+        if (i < C::WROWS) *(uint4*)&Ws[kk][co][seg] = g.w[k];
+    }
+}
+
+template <int WB, int PXB>
+__global__ void __launch_bounds__(2 * PXB)
+conv3x3_fwd_patch_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint16_t* __restrict__ w,
+                    const float* __restrict__ bias, int Cout, int relu, uint16_t* __restrict__ y) {
+    using C = PatchCfg<WB, PXB>;
+    __shared__ __attribute__((aligned(16))) uint16_t Ps[C::PIX][kPatchKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[9][kPatchCo][kPatchKP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    // block -> (image, first row, first column) of its R x WB output pixels
+    const int segs = W / WB, bands = H / C::R;
+    int t = blockIdx.x;
+    const int n = t / (bands * segs);
+    t -= n * bands * segs;
+    const int y0 = (t / segs) * C::R, x0 = (t % segs) * WB;
+    const int co0 = blockIdx.y * kPatchCo;
+    const int seg = (tid & 3) * 8;
+    // patch loads: item i = tid + NTH k -> patch pixel i >> 2, segment seg;
+    // items past the patch or pixels outside the image load the first pixel
+    // and are replaced by zero
+    int poff[C::PL];
+    bool pval[C::PL];
+#pragma unroll
+    for (int k = 0; k < C::PL; ++k) {
+        const int i = (tid + C::NTH * k) >> 2;
+        const int pr = i / C::PC, pc = i - pr * C::PC;
+        const int sy = y0 - 1 + pr, sx = x0 - 1 + pc;
+        pval[k] = i < C::PIX && sy >= 0 && sy < H && sx >= 0 && sx < W;
+        poff[k] = pval[k] ? ((n * H + sy) * W + sx) : 0;
+    }
+    PatchRegs<C::PL, C::WL> g;
+    const int nchunk = Cin / 32;
+    // a wavefront's 4 pixel fragments of 16 (rows of the output region) and
+    // their patch positions
+    int frag_base[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int q = wm * 64 + 16 * f + (lane & 15);
+        const int rr = q / WB, cc = q - rr * WB;
+        frag_base[f] = rr * C::PC + cc;
+    }
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#define PATCH_COMPUTE()                                                                      \
+    _Pragma("unroll") for (int kk = 0; kk < 9; ++kk) {                                       \
+        const int sh = (kk / 3) * C::PC + (kk % 3);                                          \
+        bf16x8 a[4], b[2];                                                                   \
+        _Pragma("unroll") for (int f = 0; f < 4; ++f)                                        \
+            a[f] = as_bf16x8(*(const uint4*)&Ps[frag_base[f] + sh][(lane >> 4) * 8]);        \
+        _Pragma("unroll") for (int j = 0; j < 2; ++j)                                        \
+            b[j] = as_bf16x8(*(const uint4*)&Ws[kk][wn * 32 + 16 * j + (lane & 15)][(lane >> 4) * 8]); \
+        _Pragma("unroll") for (int f = 0; f < 4; ++f)                                        \
+            _Pragma("unroll") for (int j = 0; j < 2; ++j)                                    \
+                acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], b[j], acc[f][j], 0, 0, 0); \
+    }
+    g = patch_load<C>(x, w, Cin, co0, tid, seg, poff, pval, 0);
+    patch_store<C>(Ps, Ws, tid, seg, g);
+    __syncthreads();
+    for (int c = 0; c < nchunk - 1; ++c) {
+        g = patch_load<C>(x, w, Cin, co0, tid, seg, poff, pval, (c + 1) * 32);   // in flight during the nine taps
+        PATCH_COMPUTE()
+        __syncthreads();    // every wavefront is done with the chunk in LDS
+        patch_store<C>(Ps, Ws, tid, seg, g);
+        __syncthreads();
+    }
+    PATCH_COMPUTE()
+#undef PATCH_COMPUTE
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int co = co0 + wn * 32 + 16 * j + (lane & 15);
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q = wm * 64 + 16 * f + 4 * (lane >> 4) + e;
+                const int rr = q / WB, cc = q - rr * WB;
+                float v = acc[f][j][e] + bb;
+                if (relu) v = v > 0.f ? v : 0.f;
+                y[((size_t)(n * H + y0 + rr) * W + x0 + cc) * Cout + co] = f2bf(v);
+            }
+    }
+}
+
 __global__ void weight_flip_k(const uint16_t* __restrict__ w, int Cout, int Cin, uint16_t* __restrict__ wt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)Cout * 9 * Cin;
@@ -776,6 +948,39 @@ extern "C" int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_
     if (Cin % 32 || Cout % 32 || ((int64_t)H * W) % 64) return kEinval;
     const int64_t P = (int64_t)N * H * W;
     if (P / 64 > 0x7fffffff) return kEinval;
+    {
+        // patch-staging kernel: W a multiple of 128, or a divisor of 128 of
+        // at least 16; 256 pixels per block where that still gives a block
+        // per compute unit (and H holds the rows), else 128
+        const int wb = W % 128 == 0 ? 128 : W;
+        const bool shape = (W % 128 == 0 || (128 % W == 0 && W >= 16)) && H % (128 / wb) == 0;
+        if (shape && Cout % 64 == 0) {
+            const int64_t t256 = H % (256 / wb) == 0 ? (int64_t)N * (H / (256 / wb)) * (W / wb) : 0;
+            const bool big = t256 * (Cout / 64) >= 256;
+            const int pxb = big ? 256 : 128;
+            const dim3 g((unsigned)((int64_t)N * (H / (pxb / wb)) * (W / wb)), Cout / 64);
+            hipStream_t st = (hipStream_t)stream;
+#define PATCH_LAUNCH(WBV, PXV) \
+    hipLaunchKernelGGL((conv3x3_fwd_patch_k<WBV, PXV>), g, dim3(2 * PXV), 0, st, x, H, W, Cin, w, bias, Cout, relu, y)
+            if (big) {
+                switch (wb) {
+                    case 128: PATCH_LAUNCH(128, 256); break;
+                    case 64: PATCH_LAUNCH(64, 256); break;
+                    case 32: PATCH_LAUNCH(32, 256); break;
+                    default: PATCH_LAUNCH(16, 256); break;
+                }
+            } else {
+                switch (wb) {
+                    case 128: PATCH_LAUNCH(128, 128); break;
+                    case 64: PATCH_LAUNCH(64, 128); break;
+                    case 32: PATCH_LAUNCH(32, 128); break;
+                    default: PATCH_LAUNCH(16, 128); break;
+                }
+            }
+#undef PATCH_LAUNCH
+            return launch_status();
+        }
+    }
     // 64 input channels per barrier pair where Cin allows it, else 32
     const bool k64 = Cin % 64 == 0;
     if (Cout % 64 == 0) {

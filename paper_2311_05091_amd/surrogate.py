@@ -457,6 +457,40 @@ def warm_start_fields(pred, phi0s: Sequence[np.ndarray], targets: Sequence[float
     return res
 
 
+def time_layers(N: int, reps: int):
+    """Forward 3x3 convolution of every layer of the network at batch N on
+    random bf16 operands: microseconds per call (HIP events around reps
+    back-to-back calls) and TFLOP/s (2 x 9 x Cin x Cout multiply-adds per
+    output pixel); printed as one JSON line per layer."""
+    import json
+    import torch
+    lib = nnlib()
+    dev = torch.device("cuda")
+    for name, cin, cout in layer_table():
+        lev = int(name[1])
+        r = RES >> lev
+        x = torch.randn(N * r * r * cin, device=dev).to(torch.bfloat16)
+        w = (torch.randn(cout * 9 * cin, device=dev) / math.sqrt(9 * cin)).to(torch.bfloat16)
+        b = torch.zeros(cout, device=dev)
+        y = torch.empty(N * r * r * cout, device=dev, dtype=torch.bfloat16)
+
+        def call():
+            _ck(lib.tpfnn_conv3x3_fwd(_p(x), N, r, r, cin, _p(w), _p(b), cout, 1, _p(y), None), "conv3x3_fwd")
+        for _ in range(3):
+            call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        fl = 2.0 * 9 * cin * cout * r * r * N
+        print(json.dumps({"layer": name, "batch": N, "H": r, "W": r, "Cin": cin, "Cout": cout, "us": round(us, 2),
+                          "tflops": round(fl / us / 1e6, 1), "frac_of_bf16_peak": round(fl / us / 1e6 / 2500.0, 4)}),
+              flush=True)
+
+
 def main(argv=None):
     """Times forward passes and training steps of the network on synthetic
     inputs (smooth random fields): ms per step and effective TFLOP/s, with
@@ -469,7 +503,11 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layers", action="store_true",
+                    help="time the forward 3x3 convolution of every layer at this batch instead")
     args = ap.parse_args(argv)
+    if args.layers:
+        return time_layers(args.batch, max(args.steps, 5))
     rng = np.random.default_rng(0)
     N = args.batch
     yy, xx = np.mgrid[0:RES, 0:RES]
