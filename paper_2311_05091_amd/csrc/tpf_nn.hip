@@ -153,7 +153,10 @@ conv3x3_fwd_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint1
 // WB + 2 columns, zero outside the image) and the 64 x 9 weights, and then
 // runs all nine taps on them: each tap's A operand is the patch shifted by
 // (ky, kx).  The next chunk's global loads are in flight (in registers) while
-// the current chunk is computed; a chunk costs two barriers.
+// the current chunk is computed.  With one LDS buffer (NB = 1) a chunk costs
+// two barriers; 256-pixel blocks whose two buffers fit in the 160 KB of a
+// compute unit (NB = 2) store the next chunk into the other buffer and need
+// one.
 // ---------------------------------------------------------------------------
 constexpr int kPatchCo = 64;
 constexpr int kPatchKP = 40;   // LDS row pitch in halfwords (32 channels + padding): the 16 rows of an operand in distinct banks
@@ -218,13 +221,15 @@ __device__ __forceinline__ void patch_store(uint16_t (*Ps)[kPatchKP], uint16_t (
     }
 }
 
-template <int WB, int PXB>
+template <int WB, int PXB, int NB>
 __global__ void __launch_bounds__(2 * PXB)
 conv3x3_fwd_patch_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const uint16_t* __restrict__ w,
                     const float* __restrict__ bias, int Cout, int relu, uint16_t* __restrict__ y) {
     using C = PatchCfg<WB, PXB>;
-    __shared__ __attribute__((aligned(16))) uint16_t Ps[C::PIX][kPatchKP];
-    __shared__ __attribute__((aligned(16))) uint16_t Ws[9][kPatchCo][kPatchKP];
+    // NB = 2: two LDS buffers (a chunk's operands are stored into the other
+    // buffer while the current one is read; one barrier per chunk)
+    __shared__ __attribute__((aligned(16))) uint16_t Ps[NB][C::PIX][kPatchKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[NB][9][kPatchCo][kPatchKP];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     // block -> (image, first row, first column) of its R x WB output pixels
@@ -264,29 +269,37 @@ conv3x3_fwd_patch_k(const uint16_t* __restrict__ x, int H, int W, int Cin, const
     for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#define PATCH_COMPUTE()                                                                      \
+#define PATCH_COMPUTE(B_)                                                                    \
     _Pragma("unroll") for (int kk = 0; kk < 9; ++kk) {                                       \
         const int sh = (kk / 3) * C::PC + (kk % 3);                                          \
         bf16x8 a[4], b[2];                                                                   \
         _Pragma("unroll") for (int f = 0; f < 4; ++f)                                        \
-            a[f] = as_bf16x8(*(const uint4*)&Ps[frag_base[f] + sh][(lane >> 4) * 8]);        \
+            a[f] = as_bf16x8(*(const uint4*)&Ps[B_][frag_base[f] + sh][(lane >> 4) * 8]);    \
         _Pragma("unroll") for (int j = 0; j < 2; ++j)                                        \
-            b[j] = as_bf16x8(*(const uint4*)&Ws[kk][wn * 32 + 16 * j + (lane & 15)][(lane >> 4) * 8]); \
+            b[j] = as_bf16x8(*(const uint4*)&Ws[B_][kk][wn * 32 + 16 * j + (lane & 15)][(lane >> 4) * 8]); \
         _Pragma("unroll") for (int f = 0; f < 4; ++f)                                        \
             _Pragma("unroll") for (int j = 0; j < 2; ++j)                                    \
                 acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], b[j], acc[f][j], 0, 0, 0); \
     }
     g = patch_load<C>(x, w, Cin, co0, tid, seg, poff, pval, 0);
-    patch_store<C>(Ps, Ws, tid, seg, g);
+    patch_store<C>(Ps[0], Ws[0], tid, seg, g);
     __syncthreads();
     for (int c = 0; c < nchunk - 1; ++c) {
         g = patch_load<C>(x, w, Cin, co0, tid, seg, poff, pval, (c + 1) * 32);   // in flight during the nine taps
-        PATCH_COMPUTE()
-        __syncthreads();    // every wavefront is done with the chunk in LDS
-        patch_store<C>(Ps, Ws, tid, seg, g);
-        __syncthreads();
+        if constexpr (NB == 2) {
+            PATCH_COMPUTE(c & 1)
+            // the other buffer was last read in chunk c - 1, before the
+            // barrier that ended it
+            patch_store<C>(Ps[(c + 1) & 1], Ws[(c + 1) & 1], tid, seg, g);
+            __syncthreads();
+        } else {
+            PATCH_COMPUTE(0)
+            __syncthreads();    // every wavefront is done with the chunk in LDS
+            patch_store<C>(Ps[0], Ws[0], tid, seg, g);
+            __syncthreads();
+        }
     }
-    PATCH_COMPUTE()
+    PATCH_COMPUTE(NB == 2 ? ((nchunk - 1) & 1) : 0)
 #undef PATCH_COMPUTE
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -960,21 +973,24 @@ extern "C" int tpfnn_conv3x3_fwd(const uint16_t* x, int32_t N, int32_t H, int32_
             const int pxb = big ? 256 : 128;
             const dim3 g((unsigned)((int64_t)N * (H / (pxb / wb)) * (W / wb)), Cout / 64);
             hipStream_t st = (hipStream_t)stream;
-#define PATCH_LAUNCH(WBV, PXV) \
-    hipLaunchKernelGGL((conv3x3_fwd_patch_k<WBV, PXV>), g, dim3(2 * PXV), 0, st, x, H, W, Cin, w, bias, Cout, relu, y)
+#define PATCH_LAUNCH(WBV, PXV, NBV)                                                             \
+    hipLaunchKernelGGL((conv3x3_fwd_patch_k<WBV, PXV, NBV>), g, dim3(2 * PXV), 0, st, x, H, W, Cin, w, bias, \
+                       Cout, relu, y)
+            // 256-pixel blocks (one per compute unit) double-buffer their LDS
+            // where two buffers fit in 160 KB (not for 128-column rows)
             if (big) {
                 switch (wb) {
-                    case 128: PATCH_LAUNCH(128, 256); break;
-                    case 64: PATCH_LAUNCH(64, 256); break;
-                    case 32: PATCH_LAUNCH(32, 256); break;
-                    default: PATCH_LAUNCH(16, 256); break;
+                    case 128: PATCH_LAUNCH(128, 256, 1); break;
+                    case 64: PATCH_LAUNCH(64, 256, 2); break;
+                    case 32: PATCH_LAUNCH(32, 256, 2); break;
+                    default: PATCH_LAUNCH(16, 256, 2); break;
                 }
             } else {
                 switch (wb) {
-                    case 128: PATCH_LAUNCH(128, 128); break;
-                    case 64: PATCH_LAUNCH(64, 128); break;
-                    case 32: PATCH_LAUNCH(32, 128); break;
-                    default: PATCH_LAUNCH(16, 128); break;
+                    case 128: PATCH_LAUNCH(128, 128, 1); break;
+                    case 64: PATCH_LAUNCH(64, 128, 1); break;
+                    case 32: PATCH_LAUNCH(32, 128, 1); break;
+                    default: PATCH_LAUNCH(16, 128, 1); break;
                 }
             }
 #undef PATCH_LAUNCH
