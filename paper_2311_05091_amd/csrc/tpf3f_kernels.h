@@ -277,8 +277,8 @@ __device__ __forceinline__ void pull18(const DomDev3F& d, int cur, int x, int y,
     gptr<const T> b = gpc<T>(d.f1[cur]);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        p[q] = pull<T>(a, q, x, y, nx, ny, d.px, d.py, N);
-        p[9 + q] = pull<T>(b, q, x, y, nx, ny, d.px, d.py, N);
+        p[q] = pull<T>(a, q, x, y, nx, ny, d.px, d.py, N, nx);
+        p[9 + q] = pull<T>(b, q, x, y, nx, ny, d.px, d.py, N, nx);
     }
 }
 
@@ -359,7 +359,7 @@ __device__ __forceinline__ void iter3f(const DomDev3F& d, const KConst3F<T>& K, 
         T gq[9];
         gptr<const T> gin = gpc<T>(d.g[cur]);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) gq[q] = pull<T>(gin, q, x, yu, nx, ny, d.px, d.py, N);
+        for (int q = 0; q < 9; ++q) gq[q] = pull<T>(gin, q, x, yu, nx, ny, d.px, d.py, N, nx);
         Lag3F<T> L;
         gptr<const T> lA = gpc<T>(d.lagA);
         L.A0x = lA[id];

@@ -181,9 +181,14 @@ static void derive_gamma(const tpf_domain_params& p, double& k, double g[3], dou
     gT = 3.0 / (1.0 / g[0] + 1.0 / g[1] + 1.0 / g[2]);
 }
 
+// Row stride of a domain's fields in elements: nx rounded up to 32, so that
+// every row starts on a cache-line boundary (a 64-lane strip load then
+// touches two lines, not three).  The columns past nx are never read.
+static int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
+
 static int validate(const tpf_domain_params& p) {
     if (p.nx < 3 || p.ny < 3) return TPF_EINVAL;
-    if ((int64_t)p.nx * p.ny * 9 >= (int64_t)1 << 31) return TPF_EINVAL;
+    if ((int64_t)pitch_of(p.nx) * p.ny * 9 >= (int64_t)1 << 31) return TPF_EINVAL;
     if (!(p.theta > 0.0 && p.theta < M_PI)) return TPF_EINVAL;
     if (!(p.d0 > 0.0 && p.d0 < 1.0)) return TPF_EINVAL;
     if (!(p.tau_phi > 0.5)) return TPF_EINVAL;
@@ -292,7 +297,7 @@ static void fill_constants(HostDomain& h) {
 // ---------------------------------------------------------------------------
 static size_t domain_bytes(const HostDomain& h, int prec) {
     const size_t e = prec == 32 ? 4 : 8;
-    const size_t N = (size_t)h.p.nx * h.p.ny;
+    const size_t N = (size_t)pitch_of(h.p.nx) * h.p.ny;   // fields: rows of pitch elements
     const bool S = h.p.rho[1] != h.p.rho[2];
     size_t b = 0;
     b += align_up(4 * 9 * N * e, 256);       // f[2], g[2]
@@ -300,7 +305,7 @@ static size_t domain_bytes(const HostDomain& h, int prec) {
     b += align_up(2 * N * e, 256);           // A
     b += align_up(N * e, 256);               // B
     if (S) b += align_up(3 * N * e, 256) + align_up(2 * N * e, 256);  // C, psi[2]
-    b += align_up(N * 8, 256);               // snap (float64)
+    b += align_up((size_t)h.p.nx * h.p.ny * 8, 256);  // snap (float64, [ny][nx])
     if (h.p.open_x) b += align_up(2 * kBndFields * (size_t)h.p.ny * e, 256);  // bnd
     return b;
 }
@@ -698,7 +703,10 @@ static int init_domain(tpf_ctx* c, int di, const double* phi1) {
 
 template <typename T>
 static int upload_phi0(tpf_ctx* c, HostDomain& h) {
-    std::vector<T> v(h.phi0.begin(), h.phi0.end());
+    const int nx = h.p.nx, ny = h.p.ny, ld = pitch_of(nx);
+    std::vector<T> v((size_t)ld * ny, T(0));   // rows of pitch elements, zero padding
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) v[(size_t)y * ld + x] = T(h.phi0[(size_t)y * nx + x]);
     HIP_OK(hipMemcpyAsync(h.dev.phi0, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     return TPF_OK;
@@ -736,8 +744,9 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
         return (void*)p;
     };
     for (auto& h : c->doms) {
-        const size_t N = (size_t)h.p.nx * h.p.ny;
+        const size_t N = (size_t)pitch_of(h.p.nx) * h.p.ny;
         DomDev& d = h.dev;
+        d.pitch = pitch_of(h.p.nx);
         char* base = (char*)take(4 * 9 * N * e);
         d.f[0] = base;
         d.f[1] = base + 9 * N * e;
@@ -755,7 +764,7 @@ extern "C" int tpf_finalize(tpf_ctx* c, void* arena, uint64_t arena_bytes) {
             d.lagC = nullptr;
             d.psi[0] = d.psi[1] = nullptr;
         }
-        d.snap = (double*)take(N * 8);
+        d.snap = (double*)take((size_t)h.p.nx * h.p.ny * 8);
         d.bnd = h.p.open_x ? take(2 * kBndFields * (size_t)h.p.ny * e) : nullptr;
         d.parity = 0;
         d.live = 1;
@@ -980,7 +989,7 @@ extern "C" int tpf_get_populations(tpf_ctx* c, int32_t id, double* f, double* g)
 
 // Checkpoint: a header, then per domain its host bookkeeping and its whole
 // arena slice (populations of both buffers, phi0, lagged fields, snapshot).
-static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '3'};
+static const char kMagic[8] = {'T', 'P', 'F', 'C', 'K', 'P', 'T', '4'};
 
 static size_t domain_slice_bytes(const tpf_ctx* c, const HostDomain& h) {
     return domain_bytes(h, c->precision);

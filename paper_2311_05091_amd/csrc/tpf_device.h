@@ -96,7 +96,9 @@ struct DomDev {
     int32_t has_s;               // rho1 != rho2: extra flux S, F_c and C are active
     int32_t bh_zero;             // BH == 0 (d0 = 1/2): H does not depend on s2a
     int32_t open_x, inlet_type;  // open ends in x (inlet 0 pressure / 1 velocity)
-    void* f[2];                  // [9][ny][nx] CH populations (ping-pong)
+    int32_t pitch;               // row stride of every field in elements: nx rounded up to 32,
+                                 // so that each row starts on a cache-line boundary
+    void* f[2];                  // [9][ny][pitch] CH populations (ping-pong)
     void* g[2];                  // [9][ny][nx] NS populations (ping-pong)
     void* phi0;                  // [ny][nx] solid field
     void* lagA;                  // [2][ny][nx] phi1 u of the previous step
@@ -173,15 +175,15 @@ __device__ __forceinline__ int map_index(int j, int n, int periodic) {
 // bounce-back, Sec. 4).
 template <typename T>
 __device__ __forceinline__ T pull(gptr<const T> fin, int q, int x, int y, int nx, int ny,
-                                  int px, int py, int N) {
+                                  int px, int py, int N, int ld) {
     int xs = x - kCx[q], ys = y - kCy[q];
     bool out = false;
     if (px) { xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs); }
     else if (xs < 0 || xs >= nx) out = true;
     if (py) { ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys); }
     else if (ys < 0 || ys >= ny) out = true;
-    if (out) return fin[kOpp[q] * N + y * nx + x];
-    return fin[q * N + ys * nx + xs];
+    if (out) return fin[kOpp[q] * N + y * ld + x];
+    return fin[q * N + ys * ld + xs];
 }
 
 // Isotropic 9-point central gradient and Laplacian on a row-major LDS tile.

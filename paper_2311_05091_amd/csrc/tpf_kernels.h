@@ -91,11 +91,12 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
                              T(0.5) * K.Kp * (Bn - lB));
 
     if constexpr (MODE == kModeMoments) {
-        const int64_t id = row + cb / sizeof(T);
+        // the moments in the caller's layout: [4][ny][nx], no row padding
+        const int64_t id = (int64_t)y * d.nx + x, Nl = (int64_t)d.nx * d.ny;
         mom_out[id] = double(ph1);
-        mom_out[N + id] = double(ux);
-        mom_out[2 * N + id] = double(uy);
-        mom_out[3 * N + id] = double(p);
+        mom_out[Nl + id] = double(ux);
+        mom_out[2 * Nl + id] = double(uy);
+        mom_out[3 * Nl + id] = double(p);
         return;
     }
     // open ends: the inner neighbours of the inlet and outlet keep their
@@ -196,9 +197,9 @@ __device__ __forceinline__ void node_update(const DomDev& d, const KConst<T>& K,
 // Pulled populations of both lattices at node (x, y).
 template <typename T>
 __device__ __forceinline__ void pull9(gptr<const T> fin, int x, int y, int nx, int ny, int px,
-                                      int py, int N, T (&out)[9]) {
+                                      int py, int N, int ld, T (&out)[9]) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) out[q] = pull(fin, q, x, y, nx, ny, px, py, N);
+    for (int q = 0; q < 9; ++q) out[q] = pull(fin, q, x, y, nx, ny, px, py, N, ld);
 }
 
 template <typename T, int TX, int TY, int NT, bool HAS_S, int MODE>
@@ -219,7 +220,7 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
     if (!d.live && MODE == kModeStep) return;
     const KConst<T> K = kconst<T>(d);
     const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
-    const int N = nx * ny;
+    const int ld = d.pitch, N = ld * ny;
     const int x0 = tile.y, y0 = tile.z;
     const int cur = (d.parity + step_offset) & 1;
     gptr<const T> fin = gpc<T>(d.f[cur]);
@@ -232,10 +233,10 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         const int wx = k % WX, wy = k / WX;
         const int sx = map_index(x0 - 2 + wx, nx, px);
         const int sy = map_index(y0 - 2 + wy, ny, py);
-        s_phi0[k] = phi0[sy * nx + sx];
-        T s = pull(fin, 0, sx, sy, nx, ny, px, py, N);
+        s_phi0[k] = phi0[sy * ld + sx];
+        T s = pull(fin, 0, sx, sy, nx, ny, px, py, N, ld);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) s += pull(fin, q, sx, sy, nx, ny, px, py, N);
+        for (int q = 1; q < 9; ++q) s += pull(fin, q, sx, sy, nx, ny, px, py, N, ld);
         s_phi1[k] = s;
     }
     __syncthreads();
@@ -254,7 +255,7 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         if (dS) {
             const int sx = map_index(x0 - 1 + vx, nx, px);
             const int sy = map_index(y0 - 1 + vy, ny, py);
-            s_psi[k] = psi_in[sy * nx + sx];
+            s_psi[k] = psi_in[sy * ld + sx];
         }
     }
     __syncthreads();
@@ -267,7 +268,7 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
         const int lx = k % TX, ly = k / TX;
         const int x = x0 + lx, y = y0 + ly;
         if (x >= nx || y >= ny) continue;
-        const int id = y * nx + x;
+        const int id = y * ld + x;
         const int ip = (ly + 2) * WX + (lx + 2);
         const int iv = (ly + 1) * VX + (lx + 1);
         T gx0, gy0, lap0, gx1, gy1, lap1, gmx, gmy, dpx = T(0), dpy = T(0);
@@ -282,8 +283,8 @@ step_kernel(const DomDev* __restrict__ doms, const int4* __restrict__ tiles, int
             lCxy = lagC[2 * N + id];
         }
         T fp[9], gq[9];
-        pull9(gin, x, y, nx, ny, px, py, N, gq);
-        pull9(fin, x, y, nx, ny, px, py, N, fp);
+        pull9(gin, x, y, nx, ny, px, py, N, ld, gq);
+        pull9(fin, x, y, nx, ny, px, py, N, ld, fp);
         node_update<T, MODE>(d, K, dS, 0, (uint32_t)id * (uint32_t)sizeof(T), N, x, y, s_phi0[ip], s_phi1[ip], gx0, gy0, lap0, gx1, gy1, lap1,
                              s_mub[iv], gmx, gmy, dpx, dpy, fp, gq, lagA[id], lagA[N + id], lagB[id],
                              lCxx, lCyy, lCxy, cur, mom_out);
@@ -364,7 +365,7 @@ __device__ __forceinline__ T ld_pop(gptr<const T> p) {
 // column part a per-lane offset.  A source row beyond a wall gives the
 // opposite population of the node itself (half-way bounce-back).
 template <typename T, bool NT>
-__device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&cb)[3], int y, int nx, int ny,
+__device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&cb)[3], int y, int ld, int ny,
                                            int py, int N, T (&out)[9]) {
     int ym = y - 1, yp = y + 1;
     bool wall = false;
@@ -376,7 +377,7 @@ __device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&c
     }
     if (!wall) {
         // source row of population q is y - cy_q: rows[1 - cy_q]
-        gptr<const T> rows[3] = {fin + (int64_t)ym * nx, fin + (int64_t)y * nx, fin + (int64_t)yp * nx};
+        gptr<const T> rows[3] = {fin + (int64_t)ym * ld, fin + (int64_t)y * ld, fin + (int64_t)yp * ld};
 #pragma unroll
         for (int q = 0; q < 9; ++q) out[q] = ld_pop<T, NT>(at_bytes(rows[1 - cy_of(q)] + (int64_t)q * N, cb[1 - cx_of(q)]));
         return;
@@ -385,7 +386,7 @@ __device__ __forceinline__ void pull9_cols(gptr<const T> fin, const uint32_t (&c
     for (int q = 0; q < 9; ++q) {
         const int ys = y - cy_of(q);
         const bool w = ys < 0 || ys >= ny;
-        const int64_t rowq = w ? (int64_t)opp_of(q) * N + (int64_t)y * nx : (int64_t)q * N + (int64_t)ys * nx;
+        const int64_t rowq = w ? (int64_t)opp_of(q) * N + (int64_t)y * ld : (int64_t)q * N + (int64_t)ys * ld;
         out[q] = *at_bytes(fin + rowq, w ? cb[1] : cb[1 - cx_of(q)]);
     }
 }
@@ -408,14 +409,14 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
                                            const uint32_t (&hb)[3], T (&fL)[9], T (&fU)[9],
                                            double* __restrict__ mom_out) {
     const int nx = d.nx, ny = d.ny, px = d.px, py = d.py;
-    const int N = nx * ny;
+    const int ld = d.pitch, N = ld * ny;
     gptr<const T> fin = gpc<T>(d.f[cur]);
     gptr<const T> phi0 = gpc<T>(d.phi0);
     const int yr = y0 - 2 + r;          // phi row loaded in this iteration
     const int yu = yr - 2;              // row updated in this iteration
     const int x = x0 + lane;
     const bool do_update = (r >= 4) && (yu < ny) && (x < nx);
-    const int64_t rowu = (int64_t)yu * nx;
+    const int64_t rowu = (int64_t)yu * ld;
     // byte offset of the updated node within its row (x < nx when updating)
     const uint32_t cu = PX ? cb[1] : (uint32_t)x * (uint32_t)sizeof(T);
 
@@ -430,20 +431,20 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     const bool load_halo = lane < 2 ? sh.own_left : (lane < 4 && sh.own_right);
     T hF[9], p0v, h0v = T(0);
     if constexpr (PX) {
-        pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, nx, ny, py, N, fL);
-        p0v = *at_bytes(phi0 + (int64_t)sy * nx, cb[1]);
+        pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, ld, ny, py, N, fL);
+        p0v = *at_bytes(phi0 + (int64_t)sy * ld, cb[1]);
         if (load_halo) {
-            pull9_cols<T, (NT & 2) != 0>(fin, hb, sy, nx, ny, py, N, hF);
-            h0v = *at_bytes(phi0 + (int64_t)sy * nx, hb[1]);
+            pull9_cols<T, (NT & 2) != 0>(fin, hb, sy, ld, ny, py, N, hF);
+            h0v = *at_bytes(phi0 + (int64_t)sy * ld, hb[1]);
         }
     } else {
         const int sx = map_index(x, nx, px);
-        pull9(fin, sx, sy, nx, ny, px, py, N, fL);
-        p0v = phi0[sy * nx + sx];
+        pull9(fin, sx, sy, nx, ny, px, py, N, ld, fL);
+        p0v = phi0[sy * ld + sx];
         if (load_halo) {
             const int hx = map_index(x0 - 2 + cxh, nx, px);
-            pull9(fin, hx, sy, nx, ny, px, py, N, hF);
-            h0v = phi0[sy * nx + hx];
+            pull9(fin, hx, sy, nx, ny, px, py, N, ld, hF);
+            h0v = phi0[sy * ld + hx];
         }
     }
 
@@ -452,8 +453,8 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     T gpl[9];
     T lAx = T(0), lAy = T(0), lB = T(0), lCxx = T(0), lCyy = T(0), lCxy = T(0);
     if (do_update) {
-        if constexpr (PX) pull9_cols<T, (NT & 1) != 0>(gpc<T>(d.g[cur]), cb, yu, nx, ny, py, N, gpl);
-        else pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, gpl);
+        if constexpr (PX) pull9_cols<T, (NT & 1) != 0>(gpc<T>(d.g[cur]), cb, yu, ld, ny, py, N, gpl);
+        else pull9(gpc<T>(d.g[cur]), x, yu, nx, ny, px, py, N, ld, gpl);
         lAx = *at_bytes(gpc<T>(d.lagA) + rowu, cu);
         lAy = *at_bytes(gpc<T>(d.lagA) + (N + rowu), cu);
         lB = *at_bytes(gpc<T>(d.lagB) + rowu, cu);
@@ -504,7 +505,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
                 if (dS) {
                     const int sx = map_index(x0 - 1 + c, nx, px);
                     const int sy = map_index(yr - 1, ny, py);
-                    sh.psi(slot3)[c] = gpc<T>(d.psi[cur])[sy * nx + sx];
+                    sh.psi(slot3)[c] = gpc<T>(d.psi[cur])[sy * ld + sx];
                 }
             }
         }
@@ -630,16 +631,17 @@ __device__ __forceinline__ void csum_merge(CSum& a, const CSum& b) {
 template <typename T, int NW>
 __device__ int persist_check(const DomDev& d, int dom, int buf, int cs, double tol, int* __restrict__ last_check,
                              double* __restrict__ stats, double* red) {
-    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    // snap in the [ny][nx] layout, populations in rows of pitch elements
+    const int nx = d.nx, ny = d.ny, N = nx * ny, ld = d.pitch, Np = ld * ny;
     gptr<const T> fin = gpc<T>(d.f[buf]);
     gptr<double> snap = gp<double>(d.snap);
     CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
     double bad = 0.0;
     for (int id = threadIdx.x; id < N; id += 64 * NW) {
         const int y = id / nx, x = id - y * nx;
-        T sum = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
+        T sum = pull(fin, 0, x, y, nx, ny, d.px, d.py, Np, ld);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) sum += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
+        for (int q = 1; q < 9; ++q) sum += pull(fin, q, x, y, nx, ny, d.px, d.py, Np, ld);
         const double v = double(sum);
         if (!isfinite(v)) bad += 1.0;
         csum_add(m, v);
@@ -912,16 +914,18 @@ template <typename T>
 __global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const double* __restrict__ phi1_in) {
     const DomDev& d = doms[dom];
     const int nx = d.nx, ny = d.ny, N = nx * ny;
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;   // node in the [ny][nx] layout of phi1_in and snap
     if (id >= N) return;
     const int x = id % nx, y = id / nx;
+    const int ld = d.pitch, Np = ld * ny;
+    const int o = y * ld + x;                                  // node in the fields' rows of pitch elements
     gptr<const T> phi0 = gpc<T>(d.phi0);
     T v0[9], v1[9];
     int k = 0;
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx, ++k) {
             int sx = map_index(x + dx, nx, d.px), sy = map_index(y + dy, ny, d.py);
-            v0[k] = phi0[sy * nx + sx];
+            v0[k] = phi0[sy * ld + sx];
             v1[k] = T(phi1_in[sy * nx + sx]);
         }
     // row-major 3x3 neighbourhood, centre at index 4, pitch 3
@@ -935,22 +939,22 @@ __global__ void init_kernel(const DomDev* __restrict__ doms, int dom, const doub
     const int par = d.parity;
     gptr<T> f = gp<T>(d.f[par]);
     gptr<T> g = gp<T>(d.g[par]);
-    f[id] = v1[4] + (w0 - T(1)) * emu;
-    for (int q = 1; q <= 4; ++q) f[q * N + id] = w1 * emu;
-    for (int q = 5; q <= 8; ++q) f[q * N + id] = w5 * emu;
-    g[id] = K.gauge;
-    for (int q = 1; q < 9; ++q) g[q * N + id] = T(0);
+    f[o] = v1[4] + (w0 - T(1)) * emu;
+    for (int q = 1; q <= 4; ++q) f[q * Np + o] = w1 * emu;
+    for (int q = 5; q <= 8; ++q) f[q * Np + o] = w5 * emu;
+    g[o] = K.gauge;
+    for (int q = 1; q < 9; ++q) g[q * Np + o] = T(0);
     gptr<T> A = gp<T>(d.lagA);
-    A[id] = T(0);
-    A[N + id] = T(0);
-    gp<T>(d.lagB)[id] = T(0);
+    A[o] = T(0);
+    A[Np + o] = T(0);
+    gp<T>(d.lagB)[o] = T(0);
     if (d.has_s) {
         gptr<T> Cl = gp<T>(d.lagC);
-        Cl[id] = T(0);
-        Cl[N + id] = T(0);
-        Cl[2 * N + id] = T(0);
-        gp<T>(d.psi[0])[id] = T(0);
-        gp<T>(d.psi[1])[id] = T(0);
+        Cl[o] = T(0);
+        Cl[Np + o] = T(0);
+        Cl[2 * Np + o] = T(0);
+        gp<T>(d.psi[0])[o] = T(0);
+        gp<T>(d.psi[1])[o] = T(0);
     }
     gp<double>(d.snap)[id] = __builtin_nan("");
 }
@@ -968,17 +972,17 @@ reduce_partials(const DomDev* __restrict__ doms, const int* __restrict__ dom_lis
                 double* __restrict__ partials) {
     const int dom = dom_list[blockIdx.y];
     const DomDev& d = doms[dom];
-    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    const int nx = d.nx, ny = d.ny, ld = d.pitch, Np = ld * ny;
     gptr<const T> fin = gpc<T>(d.f[d.parity]);
-    gptr<double> snap = gp<double>(d.snap);
+    gptr<double> snap = gp<double>(d.snap);   // [ny][nx]
     CSum m = {0, 0}, r = {0, 0}, n2 = {0, 0};
     double bad = 0.0;
     for (int y = blockIdx.x; y < ny; y += gridDim.x) {
         for (int x = threadIdx.x; x < nx; x += kRedThreads) {
             const int id = y * nx + x;
-            T s = pull(fin, 0, x, y, nx, ny, d.px, d.py, N);
+            T s = pull(fin, 0, x, y, nx, ny, d.px, d.py, Np, ld);
 #pragma unroll
-            for (int q = 1; q < 9; ++q) s += pull(fin, q, x, y, nx, ny, d.px, d.py, N);
+            for (int q = 1; q < 9; ++q) s += pull(fin, q, x, y, nx, ny, d.px, d.py, Np, ld);
             const double v = double(s);
             if (!isfinite(v)) bad += 1.0;
             csum_add(m, v);
@@ -1051,14 +1055,14 @@ __global__ void open_bc_kernel(const DomDev* __restrict__ doms, const int* __res
     if ((int)blockIdx.y >= n_open) return;
     const DomDev& d = doms[open[blockIdx.y]];
     if (!d.live) return;
-    const int nx = d.nx, ny = d.ny, N = nx * ny;
+    const int nx = d.nx, ny = d.ny, ld = d.pitch, N = ld * ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * ny) return;
     const int side = t / ny, y = t - side * ny;
     const KConst<T> K = kconst<T>(d);
     const T c2 = K.c2;
     const int out = (d.parity + step_offset + 1) & 1;
-    const int ib = y * nx + (side ? nx - 1 : 0), in = y * nx + (side ? nx - 2 : 1);
+    const int ib = y * ld + (side ? nx - 1 : 0), in = y * ld + (side ? nx - 2 : 1);
     gptr<const T> bn = gpc<T>(d.bnd) + side * kBndFields * ny + y;
     const T p1n = bn[kBndPhi1 * ny], mbn = bn[kBndMub * ny], uxn = bn[kBndUx * ny], uyn = bn[kBndUy * ny];
     const T pn = bn[kBndP * ny], Sxn = bn[kBndSx * ny], Syn = bn[kBndSy * ny];
@@ -1147,11 +1151,12 @@ __global__ void __launch_bounds__(kRedThreads)
 flow_partials(const DomDev* __restrict__ doms, int dom, const double* __restrict__ mom,
               double* __restrict__ partials) {
     const DomDev& d = doms[dom];
-    const int N = d.nx * d.ny;
-    gptr<const T> phi0 = gpc<T>(d.phi0);
+    const int N = d.nx * d.ny;                 // mom in the [ny][nx] layout
+    gptr<const T> phi0 = gpc<T>(d.phi0);       // rows of pitch elements
     CSum a = {0, 0}, b = {0, 0}, c = {0, 0};
     for (int id = blockIdx.x * kRedThreads + threadIdx.x; id < N; id += gridDim.x * kRedThreads) {
-        const double p0 = double(phi0[id]);
+        const int y = id / d.nx, x = id - y * d.nx;
+        const double p0 = double(phi0[y * d.pitch + x]);
         if (p0 > 0.5) continue;
         const double ux = mom[N + id], p1 = mom[id];
         csum_add(a, ux);
@@ -1190,12 +1195,15 @@ static __global__ void flow_final(const double* __restrict__ partials, int nblk,
 template <typename T>
 __global__ void export_populations(const DomDev* __restrict__ doms, int dom, double* __restrict__ out) {
     const DomDev& d = doms[dom];
-    const int N = d.nx * d.ny;
+    const int N = d.nx * d.ny, Np = d.pitch * d.ny;   // out: [2][9][ny][nx]
     gptr<const T> f = gpc<T>(d.f[d.parity]);
     gptr<const T> g = gpc<T>(d.g[d.parity]);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 9 * N; i += gridDim.x * blockDim.x) {
-        out[i] = double(f[i]);
-        out[9 * N + i] = double(g[i]);
+        const int q = i / N, id = i - q * N;
+        const int y = id / d.nx, x = id - y * d.nx;
+        const int o = q * Np + y * d.pitch + x;
+        out[i] = double(f[o]);
+        out[9 * N + i] = double(g[o]);
     }
 }
 
