@@ -181,10 +181,11 @@ static void derive_gamma(const tpf_domain_params& p, double& k, double g[3], dou
     gT = 3.0 / (1.0 / g[0] + 1.0 / g[1] + 1.0 / g[2]);
 }
 
-// Row stride of a domain's fields in elements: nx rounded up to 32, so that
-// every row starts on a cache-line boundary (a 64-lane strip load then
-// touches two lines, not three).  The columns past nx are never read.
-static int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
+// Row stride of a domain's fields in elements: nx rounded up to 64, the
+// width of a strip, so that every strip row starts on a cache-line boundary
+// (a 64-lane load then touches whole lines, not a partial line at each end).
+// The columns past nx are never read.
+static int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 static int validate(const tpf_domain_params& p) {
     if (p.nx < 3 || p.ny < 3) return TPF_EINVAL;

@@ -96,8 +96,8 @@ struct DomDev {
     int32_t has_s;               // rho1 != rho2: extra flux S, F_c and C are active
     int32_t bh_zero;             // BH == 0 (d0 = 1/2): H does not depend on s2a
     int32_t open_x, inlet_type;  // open ends in x (inlet 0 pressure / 1 velocity)
-    int32_t pitch;               // row stride of every field in elements: nx rounded up to 32,
-                                 // so that each row starts on a cache-line boundary
+    int32_t pitch;               // row stride of every field in elements: nx rounded up to 64,
+                                 // so that each strip row starts on a cache-line boundary
     void* f[2];                  // [9][ny][pitch] CH populations (ping-pong)
     void* g[2];                  // [9][ny][nx] NS populations (ping-pong)
     void* phi0;                  // [ny][nx] solid field
