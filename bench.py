@@ -277,13 +277,33 @@ def main():
     if args.tile:
         ctx.set_tile(args.tile)
     elif len(specs) > 1 and args.launch_mode == 0:
-        # a batch of many sizes: one tile code per size class
-        ctx.autotune_classes(steps=10, cache_path=args.tile_cache)
-        per_class = {}
-        for i, sp in enumerate(specs):
-            key = size_class(args.precision, sp.nx, sp.ny, sp.rho[1] != sp.rho[2])
-            per_class.setdefault(key, [ctx.domain_tile(i), 0])[1] += 1
-        print("[bench] tile per size class (code, domains): %s" % per_class, flush=True)
+        # a batch of many sizes: one tile code per size class, or the best
+        # single code for the whole batch, whichever steps the batch faster
+        # (each class is timed alone, which does not see how the classes
+        # share the device)
+        import tempfile
+        cache = args.tile_cache or os.path.join(tempfile.mkdtemp(prefix="tpf_tiles_"), "tiles.json")
+
+        def batch_ms(n=20):
+            ctx.step(5)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.step(n)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / n * 1e3
+
+        ctx.autotune_classes(steps=10, cache_path=cache)
+        t_class = batch_ms()
+        ctx.autotune(steps=10)
+        t_single = batch_ms()
+        print("[bench] batch step with per-class codes %.3f ms, one code %.3f ms" % (t_class, t_single), flush=True)
+        if t_class <= t_single:
+            ctx.autotune_classes(steps=10, cache_path=cache)   # the cached choice, no timing
+            per_class = {}
+            for i, sp in enumerate(specs):
+                key = size_class(args.precision, sp.nx, sp.ny, sp.rho[1] != sp.rho[2])
+                per_class.setdefault(key, [ctx.domain_tile(i), 0])[1] += 1
+            print("[bench] tile per size class (code, domains): %s" % per_class, flush=True)
     else:
         ctx.autotune(steps=30)
     code, tx, ty = ctx.tile()
