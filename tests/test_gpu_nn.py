@@ -84,13 +84,14 @@ def test_mfma_operand_layout():
                                                  (8, 64, 64, 256, 128, 1), (8, 32, 32, 256, 256, 1),
                                                  (2, 32, 32, 32, 384, 0), (1, 4, 256, 64, 64, 1),
                                                  (2, 16, 128, 32, 64, 1), (8, 128, 128, 32, 64, 1),
-                                                 (16, 32, 32, 64, 256, 0)])
+                                                 (16, 32, 32, 64, 256, 0), (12, 32, 32, 64, 256, 1)])
 def test_conv_forward(N, H, W, Cin, Cout, relu):
     """Output channels that are a multiple of 64 take the patch-staging
     kernel where the width allows (W a multiple of 128, or 16, 32, 64 with
     the rows to fill 128 pixels): widths 16, 32, 64, 128 and 256 here, with
-    256-pixel blocks at batch 8 (W = 64, 128) and 16 (W = 32); the others
-    (W = 8) take the K-step kernels."""
+    256-pixel blocks at batch 8 (W = 64, 128) and 16 (W = 32) and 128-pixel
+    blocks elsewhere (12 x 32 x 32 among them); the others (W = 8) take the
+    K-step kernels."""
     _say("conv fwd", N, H, W, Cin, Cout)
     torch = _torch()
     x = O.bf16_round(rng.normal(size=(N, H, W, Cin)))

@@ -93,29 +93,55 @@ def _run_pin(tmp_path, name, src_text, pin, src3_text=None, src3f_text=None):
     c3f.write_text(src3f_text if src3f_text is not None else open(SRC3F).read())
     subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c),
                            str(c3), str(c3f), "-lm"])
-    env = dict(os.environ, TPF_ORACLE_LIB=str(so))
+    env = dict(os.environ, TPF_ORACLE_LIB=str(so), OMP_NUM_THREADS=str(_THREADS))
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
-                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
 
 
-def test_unchanged_oracle_passes_through_the_harness(tmp_path):
-    r = _run_pin(tmp_path, "control", open(SRC).read(), NORMAL)
+# The planted mistakes are independent: all of them are compiled and their
+# pins run once per module, _WORKERS at a time with _THREADS OpenMP threads
+# each; every test item then checks its own result.
+_WORKERS, _THREADS = 4, 2
+
+
+def _cases():
+    src, src3, src3f = open(SRC).read(), open(SRC3).read(), open(SRC3F).read()
+    out = {"control": (src, NORMAL, None, None)}
+    for name, orig, repl, pin in MUTANTS:
+        out[name] = (src.replace(orig, repl), pin, None, None)
+    for name, orig, repl, pin in MUTANTS3:
+        out[name] = (src, pin, src3.replace(orig, repl), None)
+    for name, orig, repl, pin in MUTANTS3F:
+        out[name] = (src, pin, None, src3f.replace(orig, repl))
+    return out
+
+
+@pytest.fixture(scope="module")
+def pin_results(tmp_path_factory):
+    from concurrent.futures import ThreadPoolExecutor
+    d = tmp_path_factory.mktemp("mutants")
+    cases = _cases()
+    with ThreadPoolExecutor(max_workers=_WORKERS) as ex:
+        futs = {name: ex.submit(_run_pin, d, name, c[0], c[1], c[2], c[3]) for name, c in cases.items()}
+        return {name: f.result() for name, f in futs.items()}
+
+
+def test_unchanged_oracle_passes_through_the_harness(pin_results):
+    r = pin_results["control"]
     assert r.returncode == 0, r.stdout[-2000:]
 
 
 @pytest.mark.parametrize("name,orig,repl,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_fails_its_pin(tmp_path, name, orig, repl, pin):
-    src = open(SRC).read()
-    assert src.count(orig) == 1, "mutation site changed: " + orig
-    r = _run_pin(tmp_path, name, src.replace(orig, repl), pin)
+def test_mutant_fails_its_pin(pin_results, name, orig, repl, pin):
+    assert open(SRC).read().count(orig) == 1, "mutation site changed: " + orig
+    r = pin_results[name]
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
 
 
 @pytest.mark.parametrize("name,orig,repl,pin", MUTANTS3, ids=[m[0] for m in MUTANTS3])
-def test_mutant_3d_fails_its_pin(tmp_path, name, orig, repl, pin):
-    src3 = open(SRC3).read()
-    assert src3.count(orig) == 1, "mutation site changed: " + orig
-    r = _run_pin(tmp_path, name, open(SRC).read(), pin, src3.replace(orig, repl))
+def test_mutant_3d_fails_its_pin(pin_results, name, orig, repl, pin):
+    assert open(SRC3).read().count(orig) == 1, "mutation site changed: " + orig
+    r = pin_results[name]
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
 
 
@@ -137,8 +163,7 @@ MUTANTS3F = [
 
 
 @pytest.mark.parametrize("name,orig,repl,pin", MUTANTS3F, ids=[m[0] for m in MUTANTS3F])
-def test_mutant_3f_fails_its_pin(tmp_path, name, orig, repl, pin):
-    src3f = open(SRC3F).read()
-    assert src3f.count(orig) == 1, "mutation site changed: " + orig
-    r = _run_pin(tmp_path, name, open(SRC).read(), pin, src3f_text=src3f.replace(orig, repl))
+def test_mutant_3f_fails_its_pin(pin_results, name, orig, repl, pin):
+    assert open(SRC3F).read().count(orig) == 1, "mutation site changed: " + orig
+    r = pin_results[name]
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-1500:])
