@@ -2,8 +2,9 @@
 batched sweep to a tolerance, dataset, two epochs of training, gate
 calibration, and the plain-vs-learned evaluation.  Checks the bookkeeping
 (step counts, retirement, fallbacks) and that the warm-started runs reach the
-same tolerance from a mass-exact initial field; the speed-up itself is
-measured by the full pipeline, not here."""
+same tolerance as the plain ones (no run capped, no restart) and end within
+0.05 rel. L2 of the plain runs' final states (measured: at most 0.002); the
+gain itself is asserted by the trained test below."""
 import sys
 
 import numpy as np
@@ -44,15 +45,24 @@ def test_warm_start_pipeline_small(tmp_path):
     pd = ev["per_domain"]
     assert len(pd["plain_steps"]) == 4 and len(pd["learned_steps"]) == 4
     assert ev["learned_nan"] == 0 and ev["plain_nan"] == 0
-    assert all(0 < s <= 4000 for s in pd["plain_steps"]) and all(0 < s <= 8000 for s in pd["learned_steps"])
+    assert ev["plain_capped"] == 0 and ev["learned_capped"] == 0 and ev["restarted"] == 0
+    assert all(0 < s < 4000 for s in pd["plain_steps"]) and all(0 < s < 4000 for s in pd["learned_steps"])
+    assert ev["final_state_rel_l2_max"] <= 0.05
     assert 0 <= ev["gated_to_plain"] <= 4
+    print("[warm] plain %s learned %s capped %d/%d final-state rel L2 %s" %
+          (pd["plain_steps"], pd["learned_steps"], ev["plain_capped"], ev["learned_capped"],
+           ["%.3g" % v for v in pd["final_state_rel_l2"]]), flush=True)
     # with a probe of the plain start first: domains converged within it skip the surrogate
     ev2 = W.evaluate(net, held, tol=1e-4, check_every=50, max_steps=4000, gate=gate, probe_steps=100,
                      log=lambda m: None)
     pd2 = ev2["per_domain"]
     assert ev2["probe_steps"] == 100 and 0 <= ev2["probe_converged"] <= 4 and ev2["learned_nan"] == 0
-    assert all(0 < s <= 8000 for s in pd2["learned_steps"])
+    assert ev2["learned_capped"] == 0 and ev2["restarted"] == 0
+    assert all(0 < s < 4000 for s in pd2["learned_steps"])
+    assert ev2["final_state_rel_l2_max"] <= 0.05
     assert sum(np.isfinite(pd2["surrogate_rel_l2"])) <= 4 - ev2["probe_converged"]
+    print("[warm] probe: learned %s capped %d final-state rel L2 %s" %
+          (pd2["learned_steps"], ev2["learned_capped"], ["%.3g" % v for v in pd2["final_state_rel_l2"]]), flush=True)
 
 
 def test_warm_start_field_is_mass_exact_and_bounded():
