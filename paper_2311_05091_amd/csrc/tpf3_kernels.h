@@ -310,6 +310,10 @@ __device__ __forceinline__ void step3_iter(const DomDev3& d, const KConst3<T>& K
     // columns take the scalar-base addressing of pull15_row
     uint32_t xb[3] = {0, 0, 0};
     T p0own;
+    // loads at the highest wavefront priority (until the NS prefetch is
+    // issued), so that a memory-bound wavefront gets its loads out before the
+    // others' arithmetic
+    __builtin_amdgcn_s_setprio(3);
     if (d.px) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) xb[k] = (uint32_t)map3(x - 1 + k, nx, 1) * (uint32_t)sizeof(T);
@@ -338,6 +342,7 @@ __device__ __forceinline__ void step3_iter(const DomDev3& d, const KConst3<T>& K
             for (int k = 0; k < 6; ++k) L.C[k] = lC[k * N + idu];
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     {
         const int i = (wy + 2) * WX + lane + 2;
         sh.phi1[slot5][i] = sum15(FL);

@@ -292,6 +292,9 @@ __device__ __forceinline__ void iter3f(const DomDev3F& d, const KConst3F<T>& K, 
     const int sy = map_index(yr, ny, d.py);
     const int s5 = r % 5;
     // ---- A. pull both CH lattices of row yr ----
+    // (at the highest wavefront priority, so that a memory-bound wavefront
+    // gets its loads out before the others' arithmetic)
+    __builtin_amdgcn_s_setprio(3);
     {
         const int sx = map_index(x0 + lane, nx, d.px);
         pull18<T>(d, cur, sx, sy, FL);
@@ -318,6 +321,7 @@ __device__ __forceinline__ void iter3f(const DomDev3F& d, const KConst3F<T>& K, 
         sh.phi0[s5][cell] = a;
         sh.phi1[s5][cell] = b;
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // ---- B. mubar_0, mubar_1 (and psi) of row yr - 1 on columns x0 - 1 .. x0 + 64 ----
     const int s3 = r % 3;

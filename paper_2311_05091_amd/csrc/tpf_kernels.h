@@ -430,6 +430,10 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
     // strip owns them
     const bool load_halo = lane < 2 ? sh.own_left : (lane < 4 && sh.own_right);
     T hF[9], p0v, h0v = T(0);
+    // loads at the highest wavefront priority (until the NS prefetch below
+    // is issued), so that a memory-bound wavefront gets its loads out before
+    // the others' arithmetic
+    __builtin_amdgcn_s_setprio(3);
     if constexpr (PX) {
         pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, ld, ny, py, N, fL);
         p0v = *at_bytes(phi0 + (int64_t)sy * ld, cb[1]);
@@ -464,6 +468,7 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
             lCxy = *at_bytes(gpc<T>(d.lagC) + (2 * (int64_t)N + rowu), cu);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
 
     // phi1 = sum of the pulled populations, into the LDS ring with phi0
     {
