@@ -33,7 +33,7 @@ struct TileShape {
 // than the 64 KB of LDS a workgroup may hold in FP64 with the S flux); 21,
 // 22: groups of 4 strips of 32 or 64 rows with the register budget left to
 // the compiler; 23, 24: code 22 with non-temporal loads of the pulled
-// populations of both lattices (23; the halo cells of a group with plain
+// populations of both lattices (23; each strip's halo cells with plain
 // loads) or of the NS lattice only (24).  Codes 3-7
 // and 11-16 (other tile sizes, a pipelined strip and a five-waves strip) were
 // never the fastest on any workload measured and are no longer built.

@@ -438,9 +438,10 @@ __device__ __forceinline__ void strip_iter(const DomDev& d, const KConst<T>& K, 
         pull9_cols<T, (NT & 2) != 0>(fin, cb, sy, ld, ny, py, N, fL);
         p0v = *at_bytes(phi0 + (int64_t)sy * ld, cb[1]);
         if (load_halo) {
-            // plain loads, not non-temporal: the halo cells are another
-            // workgroup's interior, and lines loaded this way stay in the
-            // caches for its read
+            // plain loads, not non-temporal: the halo cells are a
+            // neighbouring strip's interior (another wavefront's or another
+            // workgroup's), and lines loaded this way stay in the caches for
+            // its read
             pull9_cols<T, false>(fin, hb, sy, ld, ny, py, N, hF);
             h0v = *at_bytes(phi0 + (int64_t)sy * ld, hb[1]);
         }
